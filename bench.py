@@ -1,0 +1,212 @@
+"""Benchmark: site updates/s of the metric semi-Lagrangian Vlasov-Poisson
+engine on one MI355X, mixed precision next to plain FP64, with the roofline
+of the dominant kernel and the CPU oracle timed on the host.
+
+A step is one drift-kick-drift step of the whole hot path over the grid
+(element predictor and records, nearest-element query + inverse map +
+six-point interpolation + column sums, cumulative-mass force, kick and
+corrector), with the resampling (remap evaluation + cubic B-spline fit)
+every n_s steps included in the timed region.  A site update is one grid
+site reconstructed in one step.
+
+Workload: 2048^2 grid on [-1, 1]^2, elements every 8th site (256^2), a seeded
+sum of 4 Gaussian halos (synthetic; it stands in for the paper's random set
+of clouds), dt = 5e-4, remap every 50 steps; the default 2000 timed steps are
+the whole run.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("site updates/s mixed vs FP64 at 2048^2 (% HBM peak); "
+          "p50/p99 solve latency")
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_1705_03750_amd/csrc/vp_kernels.hpp",
+              "paper_1705_03750_amd/csrc/vp_engine.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recon_algorithmic_bytes(n: int, s: int, fbytes: int) -> dict:
+    """Bytes one launch of the transport reconstruction must move: F_ini
+    read once, each element's query data (position, A, H: 12 doubles) read
+    once, and the column partial sums (one double per column per 64-row
+    group) written once."""
+    E = (n // s) ** 2
+    ngy = n // 64 + 1
+    b_f = n * n * fbytes
+    b_e = E * 12 * 8
+    b_p = ngy * n * 8
+    return {"F_ini": b_f, "elements": b_e, "partials": b_p,
+            "total": b_f + b_e + b_p}
+
+
+def run_gpu(precision: str, cfg, f0, steps: int, warmup: int, prof: bool):
+    import torch
+    import paper_1705_03750_amd as vp
+    p = cfg.params(precision)
+    run = vp.VlasovRun(device="cuda:0", **{k: v for k, v in p.items()
+                                           if k != "precision"},
+                       precision=precision)
+    f0t = torch.as_tensor(f0, device="cuda:0")
+    run.init_conditions(f0t)
+    if warmup:
+        run.step(warmup)
+    run.init_conditions(f0t)        # timed region = the run from t = 0
+    run.sync()
+    torch.cuda.synchronize()
+    if prof:
+        run.prof_begin(steps + 8)
+    t0 = time.perf_counter()
+    run.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = run.prof_end() if prof else None
+    run.sync()
+    diag = run.diagnostics()
+    dt = t1 - t0
+    return {"seconds": dt, "ms_per_step": 1e3 * dt / steps,
+            "value": cfg.n * cfg.n * steps / dt, "kernels": kern,
+            "diag": diag}
+
+
+def cpu_baseline(cfg, f0, steps: int, threads: int):
+    import oracle
+    used = oracle.set_threads(threads)
+    p = cfg.params()
+    p.pop("precision")
+    o = oracle.Oracle(**p)
+    o.init_conditions(f0)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": cfg.n * cfg.n * steps / dt, "unit": "site updates/s",
+            "cores": used, "kind": "oracle",
+            "sample": f"{steps} steps of the same 2048^2 run from t = 0 "
+                      f"(remap at step {cfg.n_s} included when reached), "
+                      f"{dt:.2f} s wall"}
+
+
+def load_traffic(kind: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "recon_traffic_c2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get(precision, {}).get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=50)
+    ap.add_argument("--cpu-threads", type=int,
+                    default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--copy-cal", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (5x), "
+                         "the reference for scaling rocprofv3 FETCH_SIZE / "
+                         "WRITE_SIZE counters to bytes")
+    args = ap.parse_args()
+    if args.copy_cal:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_bytes_read": src.numel() * 4,
+                          "copy_bytes_written": src.numel() * 4,
+                          "seconds_per_copy": dt,
+                          "GBps_read_plus_write": 2 * src.numel() * 4 / dt / 1e9}))
+        return
+    if args.gpus != 1:
+        print("bench.py: this engine runs one run on one GPU; multi-GPU "
+              "figures are not part of this build (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import workloads as W
+    cfg, f0 = W.config("c2_halos_2048")
+    res = {}
+    for prec in (["mixed", "fp64"] if args.only is None else [args.only]):
+        res[prec] = run_gpu(prec, cfg, f0, args.steps, args.warmup, True)
+        print(f"[bench] {prec}: {res[prec]['ms_per_step']:.4f} ms/step, "
+              f"{res[prec]['value']:.4e} site updates/s", file=sys.stderr,
+              flush=True)
+    main_prec = "mixed" if "mixed" in res else "fp64"
+    m = res[main_prec]
+    fb = 4 if main_prec == "mixed" else 8
+    ms_recon, n_recon = m["kernels"]["recon"]
+    avg_s = ms_recon / n_recon / 1e3
+    alg = recon_algorithmic_bytes(cfg.n, cfg.s, fb)
+    achieved = alg["total"] / avg_s / 1e9
+    traffic = load_traffic("recon", main_prec)
+    out = {
+        "metric": METRIC,
+        "value": m["value"],
+        "unit": "site updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 f/interp + f64 elements/query/force" if main_prec ==
+        "mixed" else "f64",
+        "data": "synthetic (seeded 4-halo sum)",
+        "config": {"workload": "c2_halos_2048: 2048^2 grid on [-1,1]^2, "
+                               "elements every 8th site, 4 Gaussian halos, "
+                               "dt 5e-4, remap every 50 steps",
+                   "grid": cfg.n, "element_stride": cfg.s, "dt": cfg.dt,
+                   "n_s": cfg.n_s, "precision": main_prec},
+        "roofline": {"bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_recon (transport reconstruction + column "
+                               "sums)",
+                     "avg_launch_us": avg_s * 1e6,
+                     "algorithmic_bytes_per_launch": alg["total"]},
+    }
+    if "fp64" in res and main_prec != "fp64":
+        f = res["fp64"]
+        fms, fn = f["kernels"]["recon"]
+        out["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"],
+                       "recon_avg_launch_us": fms / fn * 1e3,
+                       "mixed_over_fp64": m["value"] / f["value"]}
+    out["kernels_ms_per_step"] = {
+        k: v[0] / args.steps for k, v in m["kernels"].items() if v[1]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, f0, args.cpu_steps,
+                                           args.cpu_threads)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,698 @@
+// vp_engine.hip -- host side of the MI355X engine: workspace carving, step
+// sequencing on the caller's stream, and the C ABI declared in vp.h.
+//
+// Every step runs: k_elem_predict (predictor drift, A = T^-1, query-block
+// lists) -> k_recon (nearest element, inverse map, six-point interpolation,
+// column sums) -> k_field (cumulative mass, force and derivatives) ->
+// k_elem_kick (TSC, kick, corrector drift); every n_s steps the resampling
+// k_elem_predict -> k_remap_eval -> k_fit_x -> k_fit_v -> k_ghost_x ->
+// k_elem_reset.  Nothing is allocated: all buffers live in the caller's
+// workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vp.h"
+#include "vp_kernels.hpp"
+
+using namespace vpk;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Layout {
+  size_t F, C, T, st, rec, cnt, lst, flags, ovf, part, colcnt, S, Mw, Ml, acc,
+      dpart, dout, tab, total;
+  size_t fbytes;  // bytes per f value
+  long long nb;
+  int nwg_x, nwg_y;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool params_ok(const vp_params *p) {
+  return p && p->nx >= 8 && p->nv >= 8 && p->sx >= 1 && p->sv >= 1 &&
+         p->nx % p->sx == 0 && p->nv % p->sv == 0 && p->dt > 0.0 &&
+         p->x_max > p->x_min && p->v_max > p->v_min && p->n_s >= 0 &&
+         p->beta >= 0.0 && p->beta <= 0.5 &&
+         (p->precision == VP_FP64 || p->precision == VP_MIXED) &&
+         (p->force_mode == VP_FORCE_SELF ||
+          p->force_mode == VP_FORCE_EXTERNAL) &&
+         std::isfinite(p->G) && p->nx <= (1 << 17) && p->nv <= (1 << 17);
+}
+
+// list capacity per 8x8 block: about twice the element count whose windows
+// reach a block when the lattice is undeformed
+int list_cap(int sx, int sv) {
+  auto per_axis = [](int s) { return (8 + 2 * s + 2) / s + 2; };
+  int c = 2 * per_axis(sx) * per_axis(sv);
+  int cap = 16;
+  while (cap < c && cap < 256) cap *= 2;
+  return cap;
+}
+
+KP make_kp(const vp_params *p) {
+  KP k{};
+  k.nx = p->nx;
+  k.nv = p->nv;
+  k.sx = p->sx;
+  k.sv = p->sv;
+  k.mx = p->nx / p->sx;
+  k.mv = p->nv / p->sv;
+  k.E = k.mx * k.mv;
+  k.ox = (p->sx / 2) % 8;
+  k.ov = (p->sv / 2) % 8;
+  k.obx = k.ox > 0;
+  k.obv = k.ov > 0;
+  k.nbx = ((p->nx - 1 - k.ox) >> 3) + k.obx + 1;
+  k.nbv = ((p->nv - 1 - k.ov) >> 3) + k.obv + 1;
+  k.ngy = ((p->nv - 1 - k.ov) >> 6) + k.obv + 1;
+  k.cap = list_cap(p->sx, p->sv);
+  k.pitch = p->nx + 2 * PX;
+  k.x_min = p->x_min;
+  k.v_min = p->v_min;
+  k.dx = (p->x_max - p->x_min) / p->nx;
+  k.dv = (p->v_max - p->v_min) / p->nv;
+  k.inv_dx = 1.0 / k.dx;
+  k.inv_dv = 1.0 / k.dv;
+  k.dxm = p->sx * k.dx;
+  k.dvm = p->sv * k.dv;
+  k.rx = 1.0 / k.dxm;
+  k.rv = 1.0 / k.dvm;
+  k.G = p->G;
+  k.dt = p->dt;
+  k.h = 0.5 * p->dt;
+  k.beta = p->beta;
+  k.force_mode = p->force_mode;
+  k.a0 = p->ext_a0;
+  k.a1 = p->ext_a1;
+  k.a2 = p->ext_a2;
+  return k;
+}
+
+Layout make_layout(const vp_params *p, const KP &k) {
+  Layout L{};
+  const size_t fb = (p->precision == VP_MIXED) ? 4 : 8;
+  L.fbytes = fb;
+  L.nb = (long long)k.nbx * k.nbv;
+  L.nwg_x = k.nbx;
+  L.nwg_y = k.ngy;
+  const size_t padded = (size_t)(k.nv + 2 * PV) * (size_t)k.pitch * fb;
+  const size_t N2 = (size_t)k.nx * k.nv;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.F = take(padded);
+  L.C = take(padded);
+  L.T = take(N2 * fb);
+  L.st = take((size_t)NSTATE * k.E * 8);
+  L.rec = take((size_t)RS * k.E * 8);
+  L.cnt = take((size_t)2 * L.nb * 4);  // two count buffers, see vp_ctx::cur
+  L.lst = take((size_t)L.nb * k.cap * 4);
+  L.flags = take(64);
+  L.ovf = take(64);
+  L.part = take((size_t)k.ngy * k.nx * 8);
+  L.colcnt = take((size_t)(k.nbx + 64) * 4);  // + the done-block counter
+  L.S = take((size_t)k.nx * 8);
+  L.Mw = take((size_t)k.nx * 8);
+  L.Ml = take((size_t)k.nx * 8);
+  L.acc = take((size_t)3 * (k.nx + 8) * 8);
+  L.dpart = take((size_t)2 * k.nbx * k.ngy * 8);
+  L.dout = take(16 * 8);
+  L.tab = take((size_t)2 * (k.nx + k.nv) * fb);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+enum ProfKind {
+  PK_PREDICT = 0, PK_RECON, PK_FIELD, PK_KICK, PK_REMAP, PK_FIT, PK_RESET,
+  PK_OTHER, PK_N
+};
+
+struct vp_ctx {
+  vp_params p;
+  KP k;
+  Layout L;
+  hipStream_t stream;
+  char *ws;
+  double t;
+  int64_t step;
+  bool ready;
+  int cur = 0;  // which of the two block-count buffers holds the live lists
+  std::string err;
+  // profiling: event pairs per kernel kind
+  bool prof = false;
+  int prof_cap = 0;
+  std::vector<hipEvent_t> ev[PK_N];
+  int ev_used[PK_N] = {};
+
+  template <typename T>
+  T *at(size_t off) const {
+    return reinterpret_cast<T *>(ws + off);
+  }
+  bool mixed() const { return p.precision == VP_MIXED; }
+  int *counts(int which) const { return at<int>(L.cnt) + (size_t)which * L.nb; }
+};
+
+namespace {
+
+int dev_fail(vp_ctx *c, hipError_t e, const char *where) {
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return VP_EDEVICE;
+}
+
+#define VP_LAUNCH_CHECK(c, where)                       \
+  do {                                                  \
+    hipError_t _e = hipGetLastError();                  \
+    if (_e != hipSuccess) return dev_fail(c, _e, where); \
+  } while (0)
+
+// Event pair around one launch when profiling is on.
+struct ProfScope {
+  vp_ctx *c;
+  int kind;
+  bool on;
+  ProfScope(vp_ctx *c_, int k) : c(c_), kind(k), on(false) {
+    if (c->prof && c->ev_used[kind] < c->prof_cap) {
+      on = true;
+      hipEventRecord(c->ev[kind][2 * c->ev_used[kind]], c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (on) {
+      hipEventRecord(c->ev[kind][2 * c->ev_used[kind] + 1], c->stream);
+      c->ev_used[kind] += 1;
+    }
+  }
+};
+
+unsigned grid_for(long long n, int bs) {
+  long long g = (n + bs - 1) / bs;
+  if (g < 1) g = 1;
+  if (g > (1ll << 30)) g = 1ll << 30;
+  return (unsigned)g;
+}
+
+// Element pass (k_elem): optional kick + corrector, optional predictor drift
+// and record/registration into count buffer `reg_buf`, optional clearing of
+// count buffer `zero_buf` (-1: none).
+int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
+                int reg_buf, int zero_buf) {
+  const KP &k = c->k;
+  ProfScope ps(c, kick ? PK_KICK : PK_PREDICT);
+  const long long nbz = zero_buf >= 0 ? c->L.nb : 0;
+  const long long n =
+      std::max<long long>(k.E, std::min<long long>(nbz, 1 << 22));
+  hipLaunchKernelGGL(k_elem, dim3(grid_for(n, 256)), dim3(256), 0, c->stream,
+                     k, c->at<double>(c->L.st), c->at<double>(c->L.acc),
+                     c->at<double>(c->L.rec),
+                     zero_buf >= 0 ? c->counts(zero_buf) : nullptr, nbz,
+                     c->counts(reg_buf), c->at<int>(c->L.lst),
+                     c->at<int>(c->L.flags), kick, drift, predict, reg);
+  VP_LAUNCH_CHECK(c, "k_elem");
+  return VP_OK;
+}
+
+// Records and block lists for the current element state (no motion).
+int launch_predict(vp_ctx *c, int drift, int reg) {
+  return launch_elem(c, 0, drift, 1, reg, c->cur, -1);
+}
+
+int launch_zero_counts(vp_ctx *c) {
+  ProfScope ps(c, PK_OTHER);
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c->L.nb, 256)), dim3(256), 0,
+                     c->stream, c->counts(c->cur), c->L.nb);
+  VP_LAUNCH_CHECK(c, "k_zero_i32");
+  return VP_OK;
+}
+
+template <typename FT, int MODE>
+int launch_recon(vp_ctx *c, void *fout, int *aout, double *rho_out) {
+  const KP &k = c->k;
+  ProfScope ps(c, PK_RECON);
+  hipLaunchKernelGGL((k_recon<FT, MODE>), dim3(c->L.nwg_x, c->L.nwg_y),
+                     dim3(512), 0, c->stream, k, c->at<double>(c->L.rec),
+                     c->counts(c->cur), c->at<int>(c->L.lst),
+                     c->at<int>(c->L.flags), c->at<FT>(c->L.F),
+                     c->at<double>(c->L.part), c->at<int>(c->L.colcnt),
+                     c->at<double>(c->L.S), reinterpret_cast<FT *>(fout), aout,
+                     c->at<double>(c->L.dpart),
+                     c->at<unsigned long long>(c->L.ovf),
+                     c->at<int>(c->L.colcnt) + k.nbx, c->at<double>(c->L.Mw),
+                     c->at<double>(c->L.Ml), c->at<double>(c->L.acc), rho_out);
+  VP_LAUNCH_CHECK(c, "k_recon");
+  return VP_OK;
+}
+
+// The reconstruction in one of its modes; the density modes also compute
+// the force (a, a', a'') and optionally write rho.
+template <int MODE>
+int recon(vp_ctx *c, void *fout, int *aout, double *rho_out = nullptr) {
+  return c->mixed() ? launch_recon<float, MODE>(c, fout, aout, rho_out)
+                    : launch_recon<double, MODE>(c, fout, aout, rho_out);
+}
+
+int launch_field(vp_ctx *c, const double *in, int in_is_rho, double *rho_out,
+                 double *a_out, double *da_out, double *d2a_out) {
+  ProfScope ps(c, PK_FIELD);
+  hipLaunchKernelGGL(k_field, dim3(1), dim3(1024), 0, c->stream, c->k, in,
+                     in_is_rho, c->at<double>(c->L.Mw), c->at<double>(c->L.Ml),
+                     c->at<double>(c->L.acc), rho_out, a_out, da_out, d2a_out);
+  VP_LAUNCH_CHECK(c, "k_field");
+  return VP_OK;
+}
+
+int launch_reset(vp_ctx *c) {
+  ProfScope ps(c, PK_RESET);
+  const long long n =
+      std::max<long long>(c->k.E, std::min<long long>(c->L.nb, 1 << 22));
+  hipLaunchKernelGGL(k_elem_reset, dim3(grid_for(n, 256)),
+                     dim3(256), 0, c->stream, c->k, c->at<double>(c->L.st),
+                     c->counts(c->cur), c->L.nb);
+  VP_LAUNCH_CHECK(c, "k_elem_reset");
+  return VP_OK;
+}
+
+template <typename FT>
+int fit_spline_t(vp_ctx *c) {
+  const KP &k = c->k;
+  ProfScope ps(c, PK_FIT);
+  FT *tab = c->at<FT>(c->L.tab);
+  FT *cpx = tab, *rix = tab + k.nx, *cpv = tab + 2 * k.nx,
+     *riv = tab + 2 * k.nx + k.nv;
+  hipLaunchKernelGGL((k_fit_x<FT>), dim3(grid_for(k.nv, 64)), dim3(64), 0,
+                     c->stream, k, c->at<FT>(c->L.F), c->at<FT>(c->L.T), cpx,
+                     rix);
+  VP_LAUNCH_CHECK(c, "k_fit_x");
+  hipLaunchKernelGGL((k_fit_v<FT>), dim3(grid_for(k.nx, 64)), dim3(64), 0,
+                     c->stream, k, c->at<FT>(c->L.T), c->at<FT>(c->L.C), cpv,
+                     riv);
+  VP_LAUNCH_CHECK(c, "k_fit_v");
+  hipLaunchKernelGGL((k_ghost_x<FT>), dim3(grid_for(k.nv + 2, 256)), dim3(256),
+                     0, c->stream, k, c->at<FT>(c->L.C));
+  VP_LAUNCH_CHECK(c, "k_ghost_x");
+  return VP_OK;
+}
+
+int fit_spline(vp_ctx *c) {
+  return c->mixed() ? fit_spline_t<float>(c) : fit_spline_t<double>(c);
+}
+
+template <typename FT, int TO_F>
+int launch_remap_t(vp_ctx *c, void *fout) {
+  ProfScope ps(c, PK_REMAP);
+  FT *out = TO_F ? reinterpret_cast<FT *>(fout) : c->at<FT>(c->L.F);
+  hipLaunchKernelGGL((k_remap_eval<FT, TO_F>), dim3(c->L.nwg_x, c->L.nwg_y),
+                     dim3(512), 0, c->stream, c->k, c->at<double>(c->L.rec),
+                     c->counts(c->cur), c->at<int>(c->L.lst),
+                     c->at<int>(c->L.flags), c->at<FT>(c->L.C), out,
+                     c->at<unsigned long long>(c->L.ovf));
+  VP_LAUNCH_CHECK(c, "k_remap_eval");
+  return VP_OK;
+}
+
+int do_remap(vp_ctx *c) {
+  int rc;
+  if ((rc = launch_predict(c, 0, 1))) return rc;
+  rc = c->mixed() ? launch_remap_t<float, 0>(c, nullptr)
+                  : launch_remap_t<double, 0>(c, nullptr);
+  if (rc) return rc;
+  if ((rc = fit_spline(c))) return rc;
+  return launch_reset(c);
+}
+
+// n drift-kick-drift steps.  The kick + corrector of a step and the
+// predictor of the next one share one element pass (k_elem) unless a
+// resampling or the end of the call comes between them, so the elements are
+// at integer time whenever control returns to the caller.
+int run_steps(vp_ctx *c, int n) {
+  int rc;
+  const bool self = c->p.force_mode == VP_FORCE_SELF;
+  bool predicted = false;
+  for (int s = 0; s < n; ++s) {
+    if (!predicted && (rc = launch_predict(c, 1, self ? 1 : 0))) return rc;
+    if (self && (rc = recon<MODE_DENSITY>(c, nullptr, nullptr))) return rc;
+    c->step += 1;
+    c->t = (double)c->step * c->p.dt;
+    const bool remap_due = c->p.n_s > 0 && c->step % c->p.n_s == 0;
+    if (!remap_due && s + 1 < n) {
+      // kick + corrector of this step, predictor of the next, lists into
+      // the other count buffer while this one is cleared
+      if ((rc = launch_elem(c, 1, 1, 1, self ? 1 : 0, c->cur ^ 1, c->cur)))
+        return rc;
+      c->cur ^= 1;
+      predicted = true;
+    } else {
+      if ((rc = launch_elem(c, 1, 0, 0, 0, c->cur, c->cur))) return rc;
+      predicted = false;
+      if (remap_due && (rc = do_remap(c))) return rc;
+    }
+  }
+  return VP_OK;
+}
+
+template <typename FT>
+void host_tables(int n, std::vector<FT> &cp, std::vector<FT> &ri) {
+  // Thomas pivots of the (1, 4, 1) system with end rows (4, 2) / (2, 4)
+  cp.assign(n, (FT)0);
+  ri.assign(n, (FT)0);
+  FT rinv = (FT)0.25;
+  ri[0] = rinv;
+  cp[0] = (FT)2 * rinv;
+  for (int i = 1; i < n; ++i) {
+    const FT sub = (i == n - 1) ? (FT)2 : (FT)1;
+    const FT den = (FT)4 - sub * cp[i - 1];
+    rinv = (FT)1 / den;
+    ri[i] = rinv;
+    cp[i] = (FT)1 * rinv;
+  }
+}
+
+template <typename FT>
+int upload_tables(vp_ctx *c) {
+  std::vector<FT> cpx, rix, cpv, riv;
+  host_tables<FT>(c->k.nx, cpx, rix);
+  host_tables<FT>(c->k.nv, cpv, riv);
+  std::vector<FT> all;
+  all.insert(all.end(), cpx.begin(), cpx.end());
+  all.insert(all.end(), rix.begin(), rix.end());
+  all.insert(all.end(), cpv.begin(), cpv.end());
+  all.insert(all.end(), riv.begin(), riv.end());
+  hipError_t e = hipMemcpyAsync(c->at<FT>(c->L.tab), all.data(),
+                                all.size() * sizeof(FT), hipMemcpyHostToDevice,
+                                c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "table upload");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "table upload");
+  return VP_OK;
+}
+
+template <typename T>
+int fill(vp_ctx *c, T *ptr, long long n, T val) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(std::min<long long>(n, 1 << 22), 256)),
+                     dim3(256), 0, c->stream, ptr, n, val);
+  VP_LAUNCH_CHECK(c, "k_fill");
+  return VP_OK;
+}
+
+int load_rows(vp_ctx *c, const double *src, int j0, int nrows) {
+  const long long n = (long long)c->k.nx * nrows;
+  const unsigned g = grid_for(std::min<long long>(n, 1 << 22), 256);
+  if (c->mixed())
+    hipLaunchKernelGGL((k_load_f0<float>), dim3(g), dim3(256), 0, c->stream,
+                       c->k, src, j0, nrows, c->at<float>(c->L.F));
+  else
+    hipLaunchKernelGGL((k_load_f0<double>), dim3(g), dim3(256), 0, c->stream,
+                       c->k, src, j0, nrows, c->at<double>(c->L.F));
+  VP_LAUNCH_CHECK(c, "k_load_f0");
+  return VP_OK;
+}
+
+int check_flags(vp_ctx *c) {
+  int flags = 0;
+  hipError_t e = hipMemcpyAsync(&flags, c->at<int>(c->L.flags), sizeof(int),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "flag read");
+  if (flags & FLAG_NUMERIC) {
+    c->err = "non-finite element state or det T <= 0 met on the device";
+    return VP_ENUMERIC;
+  }
+  return VP_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int vp_footprint(const vp_params *p, size_t *bytes) {
+  if (!params_ok(p) || !bytes) return VP_EINVAL;
+  KP k = make_kp(p);
+  *bytes = make_layout(p, k).total;
+  return VP_OK;
+}
+
+int vp_create(const vp_params *p, void *dev_workspace, size_t bytes,
+              void *hip_stream, vp_ctx **out) {
+  if (!out) return VP_EINVAL;
+  *out = nullptr;
+  if (!params_ok(p)) {
+    g_create_error = "invalid parameters";
+    return VP_EINVAL;
+  }
+  if (!dev_workspace) {
+    g_create_error = "null workspace";
+    return VP_EINVAL;
+  }
+  KP k = make_kp(p);
+  Layout L = make_layout(p, k);
+  if (bytes < L.total) {
+    g_create_error = "workspace smaller than vp_footprint";
+    return VP_ENOMEM;
+  }
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0) {
+    g_create_error = "workspace must be 256-byte aligned";
+    return VP_EINVAL;
+  }
+  vp_ctx *c = new (std::nothrow) vp_ctx();
+  if (!c) return VP_ENOMEM;
+  c->p = *p;
+  c->k = k;
+  c->L = L;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ws = reinterpret_cast<char *>(dev_workspace);
+  c->t = 0.0;
+  c->step = 0;
+  c->ready = false;
+  // zero the whole workspace once (F padding, counts, flags, counters), then
+  // the spline pivot tables and the initial elements
+  int rc = fill<int>(c, c->at<int>(0), (long long)(L.total / 4), 0);
+  if (!rc)
+    rc = c->mixed() ? upload_tables<float>(c) : upload_tables<double>(c);
+  if (!rc) rc = launch_reset(c);
+  if (rc) {
+    g_create_error = c->err;
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return VP_OK;
+}
+
+int vp_destroy(vp_ctx *c) {
+  if (!c) return VP_EINVAL;
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  delete c;
+  return e == hipSuccess ? VP_OK : VP_EDEVICE;
+}
+
+int vp_init_conditions(vp_ctx *c, const double *f0, int f0_on_device) {
+  if (!c || !f0) return VP_EINVAL;
+  const int nx = c->k.nx, nv = c->k.nv;
+  int rc;
+  if (f0_on_device) {
+    if ((rc = load_rows(c, f0, 0, nv))) return rc;
+  } else {
+    // host input: stage row blocks through the spline-coefficient buffer,
+    // whose contents the fit below rewrites
+    const size_t stage_bytes = c->L.T - c->L.C;
+    const int rows = (int)std::min<size_t>(nv, stage_bytes / ((size_t)nx * 8));
+    double *stage = c->at<double>(c->L.C);
+    for (int j0 = 0; j0 < nv; j0 += rows) {
+      const int nr = std::min(rows, nv - j0);
+      hipError_t e = hipMemcpyAsync(stage, f0 + (size_t)j0 * nx,
+                                    (size_t)nr * nx * sizeof(double),
+                                    hipMemcpyHostToDevice, c->stream);
+      if (e != hipSuccess) return dev_fail(c, e, "f0 upload");
+      if ((rc = load_rows(c, stage, j0, nr))) return rc;
+      e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return dev_fail(c, e, "f0 upload");
+    }
+  }
+  if ((rc = fit_spline(c))) return rc;
+  if ((rc = launch_reset(c))) return rc;
+  c->t = 0.0;
+  c->step = 0;
+  c->ready = true;
+  return VP_OK;
+}
+
+int vp_step(vp_ctx *c, int nsteps) {
+  if (!c) return VP_EINVAL;
+  if (!c->ready) return VP_ESTATE;
+  if (nsteps < 0) return VP_EINVAL;
+  return run_steps(c, nsteps);
+}
+
+int vp_remap(vp_ctx *c) {
+  if (!c) return VP_EINVAL;
+  if (!c->ready) return VP_ESTATE;
+  return do_remap(c);
+}
+
+int vp_reconstruct_f(vp_ctx *c, int scheme, void *f_out_dev) {
+  if (!c || !f_out_dev) return VP_EINVAL;
+  if (!c->ready) return VP_ESTATE;
+  if (scheme != VP_SCHEME_TRANSPORT && scheme != VP_SCHEME_REMAP)
+    return VP_EINVAL;
+  int rc;
+  if ((rc = launch_predict(c, 0, 1))) return rc;
+  if (scheme == VP_SCHEME_TRANSPORT) {
+    rc = recon<MODE_F>(c, f_out_dev, nullptr);
+  } else {
+    rc = c->mixed() ? launch_remap_t<float, 1>(c, f_out_dev)
+                    : launch_remap_t<double, 1>(c, f_out_dev);
+  }
+  if (rc) return rc;
+  return launch_zero_counts(c);
+}
+
+int vp_density(vp_ctx *c, double *rho_out_dev) {
+  if (!c || !rho_out_dev) return VP_EINVAL;
+  if (!c->ready) return VP_ESTATE;
+  int rc;
+  if ((rc = launch_predict(c, 0, 1))) return rc;
+  if ((rc = recon<MODE_DENSITY>(c, nullptr, nullptr, rho_out_dev))) return rc;
+  return launch_zero_counts(c);
+}
+
+int vp_poisson(vp_ctx *c, const double *rho, double *a, double *da,
+               double *d2a) {
+  if (!c || !rho || !a || !da || !d2a) return VP_EINVAL;
+  return launch_field(c, rho, 1, nullptr, a, da, d2a);
+}
+
+int vp_diagnostics(vp_ctx *c, vp_diag *out) {
+  if (!c || !out) return VP_EINVAL;
+  if (!c->ready) return VP_ESTATE;
+  int rc;
+  if ((rc = launch_predict(c, 0, 1))) return rc;
+  if ((rc = recon<MODE_DIAG>(c, nullptr, nullptr))) return rc;
+  if ((rc = launch_zero_counts(c))) return rc;
+  hipLaunchKernelGGL(k_diag, dim3(1), dim3(1024), 0, c->stream, c->k,
+                     c->at<double>(c->L.dpart),
+                     (long long)c->L.nwg_x * c->L.nwg_y,
+                     c->at<double>(c->L.Ml), c->at<double>(c->L.acc),
+                     c->at<double>(c->L.st), c->at<double>(c->L.dout));
+  VP_LAUNCH_CHECK(c, "k_diag");
+  double h[8];
+  unsigned long long ovf = 0;
+  hipError_t e = hipMemcpyAsync(h, c->at<double>(c->L.dout), 5 * sizeof(double),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&ovf, c->at<unsigned long long>(c->L.ovf), sizeof(ovf),
+                       hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "diagnostics read");
+  out->mass = h[0];
+  out->e_kin = h[1];
+  out->e_pot = h[2];
+  out->energy = h[1] + h[2];
+  out->entropy = h[3];
+  out->max_det_dev = h[4];
+  out->t = c->t;
+  out->step = c->step;
+  out->overflow_blocks = (int64_t)ovf;
+  return check_flags(c);
+}
+
+int vp_get_elements(vp_ctx *c, double *el) {
+  if (!c || !el) return VP_EINVAL;
+  hipError_t e = hipMemcpyAsync(el, c->at<double>(c->L.st),
+                                (size_t)NSTATE * c->k.E * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "get_elements");
+  return VP_OK;
+}
+
+int vp_set_elements(vp_ctx *c, const double *el) {
+  if (!c || !el) return VP_EINVAL;
+  hipError_t e = hipMemcpyAsync(c->at<double>(c->L.st), el,
+                                (size_t)NSTATE * c->k.E * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "set_elements");
+  return VP_OK;
+}
+
+int vp_get_assignment(vp_ctx *c, int32_t *assign) {
+  if (!c || !assign) return VP_EINVAL;
+  int rc;
+  if ((rc = launch_predict(c, 0, 1))) return rc;
+  if ((rc = recon<MODE_ASSIGN>(c, nullptr, assign))) return rc;
+  return launch_zero_counts(c);
+}
+
+int vp_time(vp_ctx *c, double *t, int64_t *step) {
+  if (!c) return VP_EINVAL;
+  if (t) *t = c->t;
+  if (step) *step = c->step;
+  return VP_OK;
+}
+
+int vp_prof_begin(vp_ctx *c, int max_launches) {
+  if (!c || max_launches < 1) return VP_EINVAL;
+  if (c->prof) return VP_ESTATE;
+  for (int k = 0; k < PK_N; ++k) {
+    c->ev[k].assign(2 * (size_t)max_launches, nullptr);
+    for (auto &e : c->ev[k]) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return dev_fail(c, r, "hipEventCreate");
+    }
+    c->ev_used[k] = 0;
+  }
+  c->prof_cap = max_launches;
+  c->prof = true;
+  return VP_OK;
+}
+
+int vp_prof_end(vp_ctx *c, double *ms, int64_t *n) {
+  if (!c || !c->prof) return VP_EINVAL;
+  hipError_t r = hipStreamSynchronize(c->stream);
+  int rc = VP_OK;
+  if (r != hipSuccess) rc = dev_fail(c, r, "prof sync");
+  for (int k = 0; k < PK_N; ++k) {
+    double tot = 0.0;
+    for (int q = 0; q < c->ev_used[k] && rc == VP_OK; ++q) {
+      float m = 0.0f;
+      r = hipEventElapsedTime(&m, c->ev[k][2 * q], c->ev[k][2 * q + 1]);
+      if (r != hipSuccess) rc = dev_fail(c, r, "hipEventElapsedTime");
+      tot += m;
+    }
+    if (ms) ms[k] = tot;
+    if (n) n[k] = c->ev_used[k];
+    for (auto &e : c->ev[k])
+      if (e) hipEventDestroy(e);
+    c->ev[k].clear();
+    c->ev_used[k] = 0;
+  }
+  c->prof = false;
+  return rc;
+}
+
+int vp_sync(vp_ctx *c) {
+  if (!c) return VP_EINVAL;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "sync");
+  return check_flags(c);
+}
+
+const char *vp_last_error(vp_ctx *c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,923 @@
+// vp_kernels.hpp -- HIP kernels (gfx950) of the metric semi-Lagrangian
+// Vlasov-Poisson engine (Colombi & Alard, arXiv:1705.03750).
+//
+// Arithmetic is written operation by operation (fma only where written; the
+// library is compiled with -ffp-contract=off) so that the FP64 path rounds
+// exactly like a plain sequential evaluation of the same formulas.
+//
+// Data layout in device memory (all inside the caller's workspace):
+//   F, C      padded [nv + 2*PV][pitch] arrays, pitch = nx + 2*PX, the grid
+//             interior starting at (PV, PX).  F's padding is zero (data
+//             outside the box); C carries mirror ghosts one site deep.
+//   state     element state, SoA [12][E] doubles.
+//   rec       per-element query record, AoS [E][RS] doubles, rebuilt after
+//             every drift: position, A = T^-1, -A/2, H (xv terms doubled),
+//             lattice position Q_m.  One record is 160 B so a wavefront loads
+//             a candidate with a few scalar loads.
+//   cnt, lst  element lists of 8x8-site query blocks: every element whose
+//             validity window can reach a block is listed in that block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vpk {
+
+constexpr int PX = 16;  // x padding of F / C (values)
+constexpr int PV = 2;   // v padding of F / C (rows)
+constexpr int RS = 20;  // doubles per element query record
+constexpr int SPAN_LIMIT = 4096;  // max query blocks one element may enter
+
+enum {
+  R_X = 0, R_V, R_AXX, R_AXV, R_AVX, R_AVV, R_NAXX, R_NAXV, R_NAVX, R_NAVV,
+  R_HXXX, R_H2XXV, R_HXVV, R_HVXX, R_H2VXV, R_HVVV, R_QMX, R_QMV, R_RX, R_RV
+};
+enum {
+  S_X = 0, S_V, S_TXX, S_TXV, S_TVX, S_TVV, S_HXXX, S_HXXV, S_HXVV, S_HVXX,
+  S_HVXV, S_HVVV, NSTATE
+};
+enum { FLAG_NUMERIC = 1, FLAG_WIDE = 2 };
+enum { MODE_DENSITY = 0, MODE_F = 1, MODE_ASSIGN = 2, MODE_DIAG = 3 };
+
+struct KP {
+  int nx, nv, sx, sv, mx, mv, E;
+  int ox, ov, obx, obv, nbx, nbv, ngy, cap, pitch;
+  double x_min, v_min, dx, dv, inv_dx, inv_dv, dxm, dvm, rx, rv;
+  double G, dt, h, beta;
+  int force_mode;
+  double a0, a1, a2;
+};
+
+__device__ __forceinline__ double site_x(const KP &p, int i) {
+  return p.x_min + ((double)i + 0.5) * p.dx;
+}
+__device__ __forceinline__ double site_v(const KP &p, int j) {
+  return p.v_min + ((double)j + 0.5) * p.dv;
+}
+// query block of a site index along one axis (blocks of 8 sites whose
+// boundaries sit o sites after a multiple of 8; a partial block 0 when o > 0)
+__device__ __forceinline__ int blk(int i, int o, int ob) {
+  return ((i - o) >> 3) + ob;
+}
+
+// ------------------------------------------------------------- elements
+
+// One element update kernel for every phase of the leapfrog (section 2.4):
+//   kick     dual TSC of a, a', a'' at the element (section 2.5), kick of v,
+//            T_v. and H_v from the half-step positions, corrector drift;
+//   predict  predictor drift (when `drift`), then the per-element inverse
+//            A = T^-1 (end of section 2.1) and the query record; when `reg`,
+//            the element enters every query block its validity window can
+//            reach.
+// Applying the corrector and the next predictor in one pass keeps the two
+// half drifts as two roundings, exactly as two separate passes would.
+// cnt_zero (nb_zero counts consumed by the previous reconstruction) is
+// cleared grid-wide; registration goes to the other count buffer.
+struct ElemState {
+  double x, v, txx, txv, tvx, tvv, hx0, hx1, hx2, hv0, hv1, hv2;
+};
+
+__device__ __forceinline__ void elem_load(const double *__restrict__ st,
+                                          size_t E, int e, ElemState &s) {
+  s.x = st[S_X * E + e];
+  s.v = st[S_V * E + e];
+  s.txx = st[S_TXX * E + e];
+  s.txv = st[S_TXV * E + e];
+  s.tvx = st[S_TVX * E + e];
+  s.tvv = st[S_TVV * E + e];
+  s.hx0 = st[S_HXXX * E + e];
+  s.hx1 = st[S_HXXV * E + e];
+  s.hx2 = st[S_HXVV * E + e];
+  s.hv0 = st[S_HVXX * E + e];
+  s.hv1 = st[S_HVXV * E + e];
+  s.hv2 = st[S_HVVV * E + e];
+}
+
+__device__ __forceinline__ void elem_store(double *__restrict__ st, size_t E,
+                                           int e, const ElemState &s) {
+  st[S_X * E + e] = s.x;
+  st[S_V * E + e] = s.v;
+  st[S_TXX * E + e] = s.txx;
+  st[S_TXV * E + e] = s.txv;
+  st[S_TVX * E + e] = s.tvx;
+  st[S_TVV * E + e] = s.tvv;
+  st[S_HXXX * E + e] = s.hx0;
+  st[S_HXXV * E + e] = s.hx1;
+  st[S_HXVV * E + e] = s.hx2;
+  st[S_HVXX * E + e] = s.hv0;
+  st[S_HVXV * E + e] = s.hv1;
+  st[S_HVVV * E + e] = s.hv2;
+}
+
+__device__ __forceinline__ void elem_drift(const KP &p, ElemState &s) {
+  s.x = fma(p.h, s.v, s.x);
+  s.txx = fma(p.h, s.tvx, s.txx);
+  s.txv = fma(p.h, s.tvv, s.txv);
+  s.hx0 = fma(p.h, s.hv0, s.hx0);
+  s.hx1 = fma(p.h, s.hv1, s.hx1);
+  s.hx2 = fma(p.h, s.hv2, s.hx2);
+}
+
+__device__ __forceinline__ void elem_kick(const KP &p,
+                                          const double *__restrict__ acc,
+                                          ElemState &s) {
+  double a, da, d2a;
+  if (p.force_mode == 1) {
+    a = fma(fma(p.a2, s.x, p.a1), s.x, p.a0);
+    da = fma(2.0 * p.a2, s.x, p.a1);
+    d2a = 2.0 * p.a2;
+  } else {
+    double u = (s.x - p.x_min) * p.inv_dx - 0.5;
+    if (!(u >= -3.0)) u = -3.0;  // also catches a NaN position
+    if (u > (double)p.nx + 2.0) u = (double)p.nx + 2.0;
+    const double fi = floor(u + 0.5);
+    const double w = u - fi;
+    const double tm = 0.5 - w, tp = 0.5 + w;
+    const double w0 = 0.5 * (tm * tm), w1 = 0.75 - w * w, w2 = 0.5 * (tp * tp);
+    const int idx = (int)fi + 4;
+    const int n8 = p.nx + 8;
+    const double *A = acc, *DA = acc + n8, *D2A = acc + 2 * n8;
+    a = fma(w2, A[idx + 1], fma(w1, A[idx], w0 * A[idx - 1]));
+    da = fma(w2, DA[idx + 1], fma(w1, DA[idx], w0 * DA[idx - 1]));
+    d2a = fma(w2, D2A[idx + 1], fma(w1, D2A[idx], w0 * D2A[idx - 1]));
+  }
+  const double dt = p.dt, kdt = dt * da;
+  s.v = fma(dt, a, s.v);
+  s.tvx = fma(kdt, s.txx, s.tvx);
+  s.tvv = fma(kdt, s.txv, s.tvv);
+  s.hv0 = fma(dt, fma(da, s.hx0, d2a * (s.txx * s.txx)), s.hv0);
+  s.hv1 = fma(dt, fma(da, s.hx1, d2a * (s.txx * s.txv)), s.hv1);
+  s.hv2 = fma(dt, fma(da, s.hx2, d2a * (s.txv * s.txv)), s.hv2);
+  elem_drift(p, s);
+}
+
+// Query record and block registration of one element; returns false when
+// the element is non-finite or det T <= 0 (flagged, not registered).
+__device__ __forceinline__ void elem_record(
+    const KP &p, const ElemState &s, int e, double *__restrict__ rec,
+    int *__restrict__ cnt, int *__restrict__ lst, int *__restrict__ flags,
+    int reg) {
+  const double det = fma(s.txx, s.tvv, -(s.txv * s.tvx));
+  const bool bad = !(det > 0.0) || !isfinite(det) || !isfinite(s.x) ||
+                   !isfinite(s.v);
+  const double inv = 1.0 / det;
+  const double axx = s.tvv * inv, axv = -s.txv * inv, avx = -s.tvx * inv,
+               avv = s.txx * inv;
+  const int k = e % p.mx, l = e / p.mx;
+  double *r = rec + (size_t)e * RS;
+  r[R_X] = s.x;
+  r[R_V] = s.v;
+  r[R_AXX] = axx;
+  r[R_AXV] = axv;
+  r[R_AVX] = avx;
+  r[R_AVV] = avv;
+  r[R_NAXX] = -0.5 * axx;
+  r[R_NAXV] = -0.5 * axv;
+  r[R_NAVX] = -0.5 * avx;
+  r[R_NAVV] = -0.5 * avv;
+  r[R_HXXX] = s.hx0;
+  r[R_H2XXV] = 2.0 * s.hx1;
+  r[R_HXVV] = s.hx2;
+  r[R_HVXX] = s.hv0;
+  r[R_H2VXV] = 2.0 * s.hv1;
+  r[R_HVVV] = s.hv2;
+  r[R_QMX] = site_x(p, p.sx * k + p.sx / 2);
+  r[R_QMV] = site_v(p, p.sv * l + p.sv / 2);
+  // Eulerian reach of the validity window |A dP| < dx_m: |dP_x| <=
+  // |Txx| dx_m + |Txv| dv_m, in site units.  The relative margin covers the
+  // rounding of l = A dP (it grows with the condition number of T), the
+  // absolute one the rounding of site and element coordinates.
+  const double tsum = fabs(s.txx) + fabs(s.txv) + fabs(s.tvx) + fabs(s.tvv);
+  const double rel = 0x1p-20 + 0x1p-40 * (tsum * tsum) * fabs(inv);
+  const double rxs = (fabs(s.txx) * p.dxm + fabs(s.txv) * p.dvm) * p.inv_dx *
+                         (1.0 + rel) + 0x1p-20;
+  const double rvs = (fabs(s.tvx) * p.dxm + fabs(s.tvv) * p.dvm) * p.inv_dv *
+                         (1.0 + rel) + 0x1p-20;
+  r[R_RX] = rxs;
+  r[R_RV] = rvs;
+  if (bad) {
+    atomicOr(flags, FLAG_NUMERIC);
+    return;
+  }
+  if (!reg) return;
+  const double cx = (s.x - p.x_min) * p.inv_dx - 0.5;
+  const double cv = (s.v - p.v_min) * p.inv_dv - 0.5;
+  const double xlo = fmax(cx - rxs, -1.0), xhi = fmin(cx + rxs, (double)p.nx);
+  const double vlo = fmax(cv - rvs, -1.0), vhi = fmin(cv + rvs, (double)p.nv);
+  const int ilo = max(0, (int)ceil(xlo)), ihi = min(p.nx - 1, (int)floor(xhi));
+  const int jlo = max(0, (int)ceil(vlo)), jhi = min(p.nv - 1, (int)floor(vhi));
+  if (ilo > ihi || jlo > jhi) return;
+  const int b0x = blk(ilo, p.ox, p.obx), b1x = blk(ihi, p.ox, p.obx);
+  const int b0v = blk(jlo, p.ov, p.obv), b1v = blk(jhi, p.ov, p.obv);
+  if ((long long)(b1x - b0x + 1) * (long long)(b1v - b0v + 1) > SPAN_LIMIT) {
+    atomicOr(flags, FLAG_WIDE);
+    return;
+  }
+  for (int bv = b0v; bv <= b1v; ++bv)
+    for (int bx = b0x; bx <= b1x; ++bx) {
+      const int b = bv * p.nbx + bx;
+      const int slot = atomicAdd(&cnt[b], 1);
+      if (slot < p.cap) lst[(size_t)b * p.cap + slot] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_elem(
+    KP p, double *__restrict__ st, const double *__restrict__ acc,
+    double *__restrict__ rec, int *__restrict__ cnt_zero, long long nb_zero,
+    int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
+    int kick, int drift, int predict, int reg) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
+  const int e = (int)gid;
+  if (e >= p.E) return;
+  const size_t E = (size_t)p.E;
+  ElemState s;
+  elem_load(st, E, e, s);
+  if (kick) elem_kick(p, acc, s);
+  if (predict && drift) elem_drift(p, s);
+  if (kick || (predict && drift)) elem_store(st, E, e, s);
+  if (predict) elem_record(p, s, e, rec, cnt_reg, lst, flags, reg);
+}
+
+// New isotropic elements (P = Q_m, T = I, H = 0) and cleared block counts.
+__global__ __launch_bounds__(256) void k_elem_reset(KP p,
+                                                    double *__restrict__ st,
+                                                    int *__restrict__ cnt,
+                                                    long long nb) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (long long b = gid; b < nb; b += gsz) cnt[b] = 0;
+  const int e = (int)gid;
+  if (e >= p.E) return;
+  const size_t E = (size_t)p.E;
+  const int k = e % p.mx, l = e / p.mx;
+  for (int s = 0; s < NSTATE; ++s) st[s * E + e] = 0.0;
+  st[S_X * E + e] = site_x(p, p.sx * k + p.sx / 2);
+  st[S_V * E + e] = site_v(p, p.sv * l + p.sv / 2);
+  st[S_TXX * E + e] = 1.0;
+  st[S_TVV * E + e] = 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_zero_i32(int *__restrict__ a,
+                                                  long long n) {
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += gsz)
+    a[i] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *__restrict__ a, long long n,
+                                              T val) {
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += gsz)
+    a[i] = val;
+}
+
+// ------------------------------------------------------------- the query
+
+// One candidate of the nearest-element query (sections 1 and 2.3): inverse
+// map of eq. (QofP) with l = A dP, validity |l| < element spacing, squared
+// Lagrangian distance of eq. (distdef) in element-spacing units; the best
+// is the smallest (d^2, id).
+__device__ __forceinline__ void query_candidate(
+    const KP &p, const double *__restrict__ r, int e, double xP, double vP,
+    double &bd, int &best, double &bdqx, double &bdqv) {
+  const double dx = xP - r[R_X], dv = vP - r[R_V];
+  const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
+  const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
+  if (fabs(lx) < p.dxm && fabs(lv) < p.dvm) {
+    const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
+    const double ux = fma(r[R_HXXX], pxx, fma(r[R_H2XXV], pxv, r[R_HXVV] * pvv));
+    const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
+    const double dqx = fma(r[R_NAXX], ux, fma(r[R_NAXV], uv, lx));
+    const double dqv = fma(r[R_NAVX], ux, fma(r[R_NAVV], uv, lv));
+    const double zx = dqx * p.rx, zv = dqv * p.rv;
+    const double d2 = fma(zx, zx, zv * zv);
+    if (d2 < bd || (d2 == bd && e < best)) {
+      bd = d2;
+      best = e;
+      bdqx = dqx;
+      bdqv = dqv;
+    }
+  }
+}
+
+// Same map without the validity test (neighbour predictions at remap).
+__device__ __forceinline__ void element_map(const KP &p,
+                                            const double *__restrict__ r,
+                                            double xP, double vP, double &dqx,
+                                            double &dqv) {
+  const double dx = xP - r[R_X], dv = vP - r[R_V];
+  const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
+  const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
+  const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
+  const double ux = fma(r[R_HXXX], pxx, fma(r[R_H2XXV], pxv, r[R_HXVV] * pvv));
+  const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
+  dqx = fma(r[R_NAXX], ux, fma(r[R_NAXV], uv, lx));
+  dqv = fma(r[R_NAVX], ux, fma(r[R_NAVV], uv, lv));
+}
+
+// Nearest element of (xP, vP) from the wave's block list (uniform over the
+// wavefront: candidate records come through scalar loads), or from all
+// elements when the list overflowed or an element was too wide to list.
+__device__ __forceinline__ int query_block(
+    const KP &p, const double *__restrict__ rec, const int *__restrict__ lst,
+    int b, int n, bool scan_all, double xP, double vP, double &dqx,
+    double &dqv) {
+  double bd = __builtin_inf();
+  int best = -1;
+  dqx = 0.0;
+  dqv = 0.0;
+  if (!scan_all) {
+    const int *L = lst + (size_t)b * p.cap;
+    for (int c = 0; c < n; ++c) {
+      const int e = __builtin_amdgcn_readfirstlane(L[c]);
+      query_candidate(p, rec + (size_t)e * RS, e, xP, vP, bd, best, dqx, dqv);
+    }
+  } else {
+    for (int e = 0; e < p.E; ++e)
+      query_candidate(p, rec + (size_t)e * RS, e, xP, vP, bd, best, dqx, dqv);
+  }
+  return best;
+}
+
+// ------------------------------------------------------- interpolations
+
+// Six-point second-order interpolation (section 2.2.1, eq. int1 with the
+// Lagrange signs) of F at index-space position (sx, sv).  F points at the
+// grid origin of a zero-padded array.
+template <typename FT>
+__device__ __forceinline__ FT int1(const KP &p, const FT *__restrict__ F,
+                                   double sx, double sv) {
+  const double fin = floor(sx + 0.5), fjn = floor(sv + 0.5);
+  if (!(fin >= -1.0 && fin <= (double)p.nx && fjn >= -1.0 &&
+        fjn <= (double)p.nv))
+    return (FT)0;
+  const double fic = floor(sx), fjc = floor(sv);
+  const int in = (int)fin, jn = (int)fjn, ic = (int)fic, jc = (int)fjc;
+  const FT dqx = (FT)(sx - fin), dqv = (FT)(sv - fjn);
+  const FT one = (FT)1, half = (FT)0.5;
+  const FT w0 = (one - dqx * dqx) - dqv * dqv;
+  const FT hx = half * dqx, hv = half * dqv;
+  const FT wxp = hx * (one + dqx), wxm = hx * (one - dqx);
+  const FT wvp = hv * (one + dqv), wvm = hv * (one - dqv);
+  const FT wc = dqx * dqv;
+  const long pt = p.pitch;
+  const FT *n0 = F + (long)jn * pt + in;
+  const FT *c0 = F + (long)jc * pt + ic;
+  const FT cross = ((c0[pt + 1] + c0[0]) - c0[1]) - c0[pt];
+  FT f = n0[0] * w0;
+  f = fma(n0[1], wxp, f);
+  f = fma(-n0[-1], wxm, f);
+  f = fma(n0[pt], wvp, f);
+  f = fma(-n0[-pt], wvm, f);
+  f = fma(cross, wc, f);
+  return f;
+}
+
+template <typename FT>
+__device__ __forceinline__ void bspline_w(double ud, FT b[4]) {
+  const FT u = (FT)ud;
+  const FT sixth = (FT)(1.0 / 6.0);
+  const FT t = (FT)1 - u;
+  const FT u2 = u * u, u3 = u2 * u;
+  b[0] = ((t * t) * t) * sixth;
+  b[1] = (((FT)3 * u3 - (FT)6 * u2) + (FT)4) * sixth;
+  b[2] = ((((FT)-3 * u3 + (FT)3 * u2) + (FT)3 * u) + (FT)1) * sixth;
+  b[3] = u3 * sixth;
+}
+
+// Cubic B-spline value (section 2.2.2) from coefficients C (padded, with
+// mirror ghosts one site deep) at index-space position (sx, sv).
+template <typename FT>
+__device__ __forceinline__ FT spline_eval(const KP &p, const FT *__restrict__ C,
+                                          double sx, double sv) {
+  if (!(sx >= 0.0 && sx <= (double)(p.nx - 1) && sv >= 0.0 &&
+        sv <= (double)(p.nv - 1)))
+    return (FT)0;
+  int i = (int)floor(sx), j = (int)floor(sv);
+  if (i > p.nx - 2) i = p.nx - 2;
+  if (j > p.nv - 2) j = p.nv - 2;
+  FT bx[4], bv[4];
+  bspline_w<FT>(sx - (double)i, bx);
+  bspline_w<FT>(sv - (double)j, bv);
+  const long pt = p.pitch;
+  const FT *c = C + (long)(j - 1) * pt + (i - 1);
+  FT f = (FT)0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const FT *cr = c + b * pt;
+    FT row = bx[0] * cr[0];
+    row = fma(bx[1], cr[1], row);
+    row = fma(bx[2], cr[2], row);
+    row = fma(bx[3], cr[3], row);
+    f = (b == 0) ? bv[0] * row : fma(bv[b], row, f);
+  }
+  return f;
+}
+
+// Monaghan kernel W (section 2.3.2).
+__device__ __forceinline__ double W_kernel(double x) {
+  if (x <= 1.0) {
+    const double x2 = x * x;
+    return fma(0.75 * x, x2, fma(-1.5, x2, 1.0));
+  }
+  if (x <= 2.0) {
+    const double t = 2.0 - x;
+    return ((0.25 * t) * t) * t;
+  }
+  return 0.0;
+}
+
+// ------------------------------------------------------------- the field
+
+// Single workgroup: S (or rho) -> rho -> M -> cumulative mass M_left (256-
+// site chunks, sequential inside, carries sequential) -> a, a', a'' on the
+// indices [-4, nx + 3] (section 2.5, eq. acccomp; centred difference over
+// 2 dx).  Optional outputs rho_out and a/da/d2a on [0, nx).
+__device__ __forceinline__ double Ml_at(const double *Ml, int nx, double Mtot,
+                                        int i) {
+  if (i < 0) return 0.0;
+  if (i >= nx) return Mtot;
+  return Ml[i];
+}
+
+// The field computation of one workgroup (any size): `in` holds S (column
+// sums) or rho; ATOMIC_IN reads it with device-coherent loads (used when
+// other workgroups of the same kernel wrote it).
+template <bool ATOMIC_IN>
+__device__ __forceinline__ void field_wg(
+    const KP &p, const double *__restrict__ in, int in_is_rho,
+    double *__restrict__ Mw, double *__restrict__ Ml, double *__restrict__ acc,
+    double *__restrict__ rho_out, double *__restrict__ a_out,
+    double *__restrict__ da_out, double *__restrict__ d2a_out, double *tot,
+    double *car) {
+  const int nx = p.nx, tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < nx; i += nt) {
+    double x;
+    if (ATOMIC_IN)
+      x = __longlong_as_double((long long)__hip_atomic_load(
+          reinterpret_cast<const unsigned long long *>(in) + i,
+          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    else
+      x = in[i];
+    const double rho = in_is_rho ? x : p.dv * x;
+    if (rho_out) rho_out[i] = rho;
+    Mw[i] = p.dx * rho;
+  }
+  __syncthreads();
+  const int nch = (nx + 255) / 256;
+  for (int c = tid; c < nch; c += nt) {
+    const int c1 = min(nx, 256 * c + 256);
+    double s = 0.0;
+    for (int i = 256 * c; i < c1; ++i) {
+      s += Mw[i];
+      Ml[i] = s;
+    }
+    tot[c] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double carry = 0.0;
+    for (int c = 0; c < nch; ++c) {
+      car[c] = carry;
+      carry = carry + tot[c];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < nx; i += nt) Ml[i] = car[i >> 8] + Ml[i];
+  __syncthreads();
+  const double Mtot = Ml[nx - 1];
+  const int n8 = nx + 8;
+  const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
+  for (int q = tid; q < n8; q += nt) {
+    const int i = q - 4;
+    const double am = p.G * ((Mtot - Ml_at(Ml, nx, Mtot, i - 1)) -
+                             Ml_at(Ml, nx, Mtot, i - 2));
+    const double a0 = p.G * ((Mtot - Ml_at(Ml, nx, Mtot, i)) -
+                             Ml_at(Ml, nx, Mtot, i - 1));
+    const double ap = p.G * ((Mtot - Ml_at(Ml, nx, Mtot, i + 1)) -
+                             Ml_at(Ml, nx, Mtot, i));
+    const double da = (ap - am) / two_dx;
+    const double d2a = ((ap + am) - 2.0 * a0) / dx2;
+    acc[q] = a0;
+    acc[n8 + q] = da;
+    acc[2 * n8 + q] = d2a;
+    if (a_out && i >= 0 && i < nx) {
+      a_out[i] = a0;
+      da_out[i] = da;
+      d2a_out[i] = d2a;
+    }
+  }
+}
+
+constexpr int FIELD_CHUNKS = 1024;  // up to 262144 columns
+
+__global__ __launch_bounds__(1024) void k_field(
+    KP p, const double *__restrict__ in, int in_is_rho, double *__restrict__ Mw,
+    double *__restrict__ Ml, double *__restrict__ acc,
+    double *__restrict__ rho_out, double *__restrict__ a_out,
+    double *__restrict__ da_out, double *__restrict__ d2a_out) {
+  __shared__ double tot[FIELD_CHUNKS];
+  __shared__ double car[FIELD_CHUNKS];
+  field_wg<false>(p, in, in_is_rho, Mw, Ml, acc, rho_out, a_out, da_out,
+                  d2a_out, tot, car);
+}
+
+// ------------------------------------------------------- reconstruction
+
+// One workgroup = 8 wavefronts stacked in v; one wavefront = one 8x8-site
+// query block (lane -> site: x = lane & 7, v = lane >> 3).  The workgroup
+// covers 8 columns x 64 rows, the row group of the fixed column-sum order.
+// In the density modes the last workgroup of each column block adds the
+// row-group partials (in increasing group order) into S, and the last of
+// those computes the force for the whole grid (field_wg), so one launch
+// covers density projection and Poisson solve.
+template <typename FT, int MODE>
+__global__ __launch_bounds__(512) void k_recon(
+    KP p, const double *__restrict__ rec, const int *__restrict__ cnt,
+    const int *__restrict__ lst, const int *__restrict__ flags,
+    const FT *__restrict__ F, double *__restrict__ part,
+    int *__restrict__ colcnt, double *__restrict__ S, FT *__restrict__ fout,
+    int *__restrict__ aout, double *__restrict__ dpart,
+    unsigned long long *__restrict__ ovf, int *__restrict__ donecnt,
+    double *__restrict__ Mw, double *__restrict__ Ml, double *__restrict__ acc,
+    double *__restrict__ rho_out) {
+  __shared__ double sf[512];
+  __shared__ double sk[512];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int bx = blockIdx.x, gy = blockIdx.y;
+  const int bv = 8 * (gy - p.obv) + p.obv + w;
+  const int i = p.ox + 8 * (bx - p.obx) + (lane & 7);
+  const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
+  const bool blk_ok = bv >= 0 && bv < p.nbv;
+  const bool live = blk_ok && i >= 0 && i < p.nx && j >= 0 && j < p.nv;
+  double f = 0.0;
+  int best = -1;
+  if (blk_ok) {
+    const int b = bv * p.nbx + bx;
+    const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
+    const bool scan_all = (n > p.cap) || (flags[0] & FLAG_WIDE);
+    if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
+    const double xP = site_x(p, i), vP = site_v(p, j);
+    double dqx, dqv;
+    best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv);
+    if (live && best >= 0) {
+      const double *r = rec + (size_t)best * RS;
+      const double Qx = r[R_QMX] + dqx, Qv = r[R_QMV] + dqv;
+      const double sx = (Qx - p.x_min) * p.inv_dx - 0.5;
+      const double sv = (Qv - p.v_min) * p.inv_dv - 0.5;
+      const FT *F0 = F + (long)PV * p.pitch + PX;
+      const FT fv = int1<FT>(p, F0, sx, sv);
+      f = (double)fv;
+      if (MODE == MODE_F) fout[(size_t)j * p.nx + i] = fv;
+    } else if (MODE == MODE_F && live) {
+      fout[(size_t)j * p.nx + i] = (FT)0;
+    }
+    if (MODE == MODE_ASSIGN && live) aout[(size_t)j * p.nx + i] = best;
+  }
+  if (MODE != MODE_DENSITY && MODE != MODE_DIAG) return;
+  if (!live) f = 0.0;
+  sf[threadIdx.x] = f;
+  if (MODE == MODE_DIAG) {
+    const double vj = live ? site_v(p, j) : 0.0;
+    sk[threadIdx.x] = vj * vj * f;
+  }
+  __syncthreads();
+  if (MODE == MODE_DIAG) {
+    // fixed-order tree sums of v^2 f and f ln|f| over the workgroup
+    __shared__ double se[512];
+    se[threadIdx.x] = (f != 0.0) ? f * log(fabs(f)) : 0.0;
+    __syncthreads();
+    for (int s = 256; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        sk[threadIdx.x] += sk[threadIdx.x + s];
+        se[threadIdx.x] += se[threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const size_t wg = (size_t)gy * gridDim.x + bx;
+      dpart[2 * wg] = sk[0];
+      dpart[2 * wg + 1] = se[0];
+    }
+  }
+  if (w == 0) {
+    // column partial of this row group: sequential over the 64 rows
+    const int ic = p.ox + 8 * (bx - p.obx) + lane;
+    if (lane < 8) {
+      double s = 0.0;
+      for (int k = 0; k < 64; ++k) s += sf[(k >> 3) * 64 + (k & 7) * 8 + lane];
+      if (ic >= 0 && ic < p.nx) part[(size_t)gy * p.nx + ic] = s;
+    }
+    // the last workgroup of this column block adds the row-group partials
+    int last = 0;
+    if (lane == 0) {
+      const int old = __hip_atomic_fetch_add(&colcnt[bx], 1, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      last = (old == p.ngy - 1);
+    }
+    last = __shfl(last, 0);
+    int lastall = 0;
+    if (last) {
+      if (lane < 8 && ic >= 0 && ic < p.nx) {
+        const unsigned long long *pu =
+            reinterpret_cast<const unsigned long long *>(part);
+        double s = 0.0;
+        for (int g = 0; g < p.ngy; ++g)
+          s += __longlong_as_double((long long)__hip_atomic_load(
+              pu + (size_t)g * p.nx + ic, __ATOMIC_RELAXED,
+              __HIP_MEMORY_SCOPE_AGENT));
+        S[ic] = s;
+      }
+      if (lane == 0) {
+        __hip_atomic_store(&colcnt[bx], 0, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        // the last column block to finish computes the field
+        const int old = __hip_atomic_fetch_add(donecnt, 1, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        lastall = (old == p.nbx - 1);
+      }
+    }
+    if (lane == 0) s_last = lastall;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  field_wg<true>(p, S, 0, Mw, Ml, acc, rho_out, nullptr, nullptr, nullptr, sf,
+                 sk);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(donecnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Resampling value at every site (section 2.3.2): nearest element, the
+// beta-restricted neighbour set (diagonals dropped when an axis needs three
+// values), W(2d)-weighted blend of their predictions Q_r, cubic B-spline of
+// F_ini at Q_r; the outermost ring is zero.  Writes F (padded interior)
+// when TO_F == 0, else f_out.
+template <typename FT, int TO_F>
+__global__ __launch_bounds__(512) void k_remap_eval(
+    KP p, const double *__restrict__ rec, const int *__restrict__ cnt,
+    const int *__restrict__ lst, const int *__restrict__ flags,
+    const FT *__restrict__ C, FT *__restrict__ Fout,
+    unsigned long long *__restrict__ ovf) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int bx = blockIdx.x, gy = blockIdx.y;
+  const int bv = 8 * (gy - p.obv) + p.obv + w;
+  if (bv < 0 || bv >= p.nbv) return;
+  const int i = p.ox + 8 * (bx - p.obx) + (lane & 7);
+  const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
+  const bool live = i >= 0 && i < p.nx && j >= 0 && j < p.nv;
+  const int b = bv * p.nbx + bx;
+  const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
+  const bool scan_all = (n > p.cap) || (flags[0] & FLAG_WIDE);
+  if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
+  const double xP = site_x(p, i), vP = site_v(p, j);
+  double dqx, dqv;
+  const int best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv);
+  if (!live) return;
+  FT val = (FT)0;
+  const bool ring = (i == 0 || j == 0 || i == p.nx - 1 || j == p.nv - 1);
+  if (!ring && best >= 0) {
+    const int l0 = best / p.mx, k0 = best - l0 * p.mx;
+    const double zx = dqx * p.rx, zv = dqv * p.rv, beta = p.beta;
+    const int xlo = (zx < beta) ? -1 : 0, xhi = (zx < -beta) ? 0 : 1;
+    const int vlo = (zv < beta) ? -1 : 0, vhi = (zv < -beta) ? 0 : 1;
+    const bool three = (xhi - xlo == 2) || (vhi - vlo == 2);
+    double sw = 0.0, sqx = 0.0, sqv = 0.0;
+    for (int dl = vlo; dl <= vhi; ++dl) {
+      for (int dk = xlo; dk <= xhi; ++dk) {
+        if (three && dk != 0 && dl != 0) continue;
+        const int k = k0 + dk, l = l0 + dl;
+        if (k < 0 || k >= p.mx || l < 0 || l >= p.mv) continue;
+        const double *r = rec + (size_t)(l * p.mx + k) * RS;
+        double ex, ev;
+        element_map(p, r, xP, vP, ex, ev);
+        const double qx = r[R_QMX] + ex, qv = r[R_QMV] + ev;
+        const double ax = ex * p.rx, av = ev * p.rv;
+        const double d = sqrt(fma(ax, ax, av * av));
+        const double wt = W_kernel(2.0 * d);
+        sw += wt;
+        sqx = fma(wt, qx, sqx);
+        sqv = fma(wt, qv, sqv);
+      }
+    }
+    double Qx, Qv;
+    if (sw > 0.0) {
+      Qx = sqx / sw;
+      Qv = sqv / sw;
+    } else {
+      const double *r = rec + (size_t)best * RS;
+      Qx = r[R_QMX] + dqx;
+      Qv = r[R_QMV] + dqv;
+    }
+    const double sx = (Qx - p.x_min) * p.inv_dx - 0.5;
+    const double sv = (Qv - p.v_min) * p.inv_dv - 0.5;
+    const FT *C0 = C + (long)PV * p.pitch + PX;
+    val = spline_eval<FT>(p, C0, sx, sv);
+  }
+  if (TO_F == 0)
+    Fout[(long)(j + PV) * p.pitch + (i + PX)] = val;
+  else
+    Fout[(size_t)j * p.nx + i] = val;
+}
+
+// Diagnostics (section 3.2): sums of the per-workgroup partials, potential
+// energy from a(i), max |det T - 1|.  out = {mass, e_kin, e_pot, entropy,
+// maxdet}.
+__global__ __launch_bounds__(1024) void k_diag(
+    KP p, const double *__restrict__ dpart, long long nwg,
+    const double *__restrict__ Ml, const double *__restrict__ acc,
+    const double *__restrict__ st, double *__restrict__ out) {
+  __shared__ double s0[1024], s1[1024], s2[1024], s3[1024];
+  const int tid = threadIdx.x;
+  double kin = 0.0, ent = 0.0, pot = 0.0, mdet = 0.0;
+  for (long long q = tid; q < nwg; q += blockDim.x) {
+    kin += dpart[2 * q];
+    ent += dpart[2 * q + 1];
+  }
+  const double Mtot = Ml[p.nx - 1];
+  const int n8 = p.nx + 8;
+  if (p.force_mode == 0) {
+    const double GM = p.G * Mtot;
+    for (int i = tid; i < p.nx; i += blockDim.x) {
+      const double a = acc[i + 4];
+      pot += a * a - GM * GM;
+    }
+  } else {
+    for (int i = tid; i < p.nx; i += blockDim.x) {
+      const double x = site_x(p, i);
+      const double phi =
+          -(x * (p.a0 + x * (0.5 * p.a1 + x * (p.a2 / 3.0))));
+      // rho(i) dx = M(i) = Ml(i) - Ml(i-1)
+      const double Mi = Ml[i] - (i > 0 ? Ml[i - 1] : 0.0);
+      pot += phi * Mi;
+    }
+  }
+  const size_t E = (size_t)p.E;
+  for (int e = tid; e < p.E; e += blockDim.x) {
+    const double det = st[S_TXX * E + e] * st[S_TVV * E + e] -
+                       st[S_TXV * E + e] * st[S_TVX * E + e];
+    mdet = fmax(mdet, fabs(det - 1.0));
+  }
+  (void)n8;
+  s0[tid] = kin;
+  s1[tid] = ent;
+  s2[tid] = pot;
+  s3[tid] = mdet;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (tid < s) {
+      s0[tid] += s0[tid + s];
+      s1[tid] += s1[tid + s];
+      s2[tid] += s2[tid + s];
+      s3[tid] = fmax(s3[tid], s3[tid + s]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double cell = p.dx * p.dv;
+    out[0] = Mtot;
+    out[1] = 0.5 * s0[0] * cell;
+    if (p.force_mode == 0)
+      out[2] = (p.G != 0.0) ? -s2[0] * p.dx / (4.0 * p.G) : 0.0;
+    else
+      out[2] = s2[0];
+    out[3] = -s1[0] * cell;
+    out[4] = s3[0];
+  }
+}
+
+// ------------------------------------------------------------- the spline
+
+// Tridiagonal (1, 4, 1) solve with end rows (4, 2) / (2, 4) along x for
+// every row (Thomas elimination; the row-independent pivots cp and 1/den are
+// precomputed).  One thread per row; the row is staged through LDS in
+// 64-value chunks so that global reads and writes stay coalesced.
+template <typename FT>
+__global__ __launch_bounds__(64) void k_fit_x(KP p, const FT *__restrict__ F,
+                                              FT *__restrict__ T,
+                                              const FT *__restrict__ cpx,
+                                              const FT *__restrict__ rix) {
+  __shared__ FT tile[64][65];
+  const int lane = threadIdx.x;
+  const int j0 = blockIdx.x * 64;
+  const int nx = p.nx, nv = p.nv;
+  const long pt = p.pitch;
+  const FT *F0 = F + (long)PV * pt + PX;
+  FT dp = (FT)0;
+  // forward sweep
+  for (int c0 = 0; c0 < nx; c0 += 64) {
+    for (int r = 0; r < 64; ++r) {
+      const int j = j0 + r, i = c0 + lane;
+      tile[r][lane] = (j < nv && i < nx) ? F0[(long)j * pt + i] : (FT)0;
+    }
+    __syncthreads();
+    const int cend = min(64, nx - c0);
+    for (int c = 0; c < cend; ++c) {
+      const int i = c0 + c;
+      const FT fv = tile[lane][c];
+      if (i == 0) {
+        dp = ((FT)6 * fv) * rix[0];
+      } else {
+        const FT sub = (i == nx - 1) ? (FT)2 : (FT)1;
+        dp = ((FT)6 * fv - sub * dp) * rix[i];
+      }
+      tile[lane][c] = dp;
+    }
+    __syncthreads();
+    for (int r = 0; r < 64; ++r) {
+      const int j = j0 + r, i = c0 + lane;
+      if (j < nv && i < nx) T[(size_t)j * nx + i] = tile[r][lane];
+    }
+    __syncthreads();
+  }
+  // back substitution, chunks in reverse
+  FT out = (FT)0;
+  const int lastc = ((nx - 1) / 64) * 64;
+  for (int c0 = lastc; c0 >= 0; c0 -= 64) {
+    for (int r = 0; r < 64; ++r) {
+      const int j = j0 + r, i = c0 + lane;
+      tile[r][lane] = (j < nv && i < nx) ? T[(size_t)j * nx + i] : (FT)0;
+    }
+    __syncthreads();
+    const int cend = min(64, nx - c0);
+    for (int c = cend - 1; c >= 0; --c) {
+      const int i = c0 + c;
+      const FT d = tile[lane][c];
+      out = (i == nx - 1) ? d : d - cpx[i] * out;
+      tile[lane][c] = out;
+    }
+    __syncthreads();
+    for (int r = 0; r < 64; ++r) {
+      const int j = j0 + r, i = c0 + lane;
+      if (j < nv && i < nx) T[(size_t)j * nx + i] = tile[r][lane];
+    }
+    __syncthreads();
+  }
+}
+
+// The same solve along v for every column (one thread per column: rows are
+// read and written coalesced), written into C with mirror ghost rows.
+template <typename FT>
+__global__ __launch_bounds__(64) void k_fit_v(KP p, const FT *__restrict__ T,
+                                              FT *__restrict__ C,
+                                              const FT *__restrict__ cpv,
+                                              const FT *__restrict__ riv) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int nx = p.nx, nv = p.nv;
+  if (i >= nx) return;
+  const long pt = p.pitch;
+  FT *C0 = C + (long)PV * pt + PX + i;
+  FT dp = ((FT)6 * T[i]) * riv[0];
+  C0[0] = dp;
+  for (int j = 1; j < nv; ++j) {
+    const FT sub = (j == nv - 1) ? (FT)2 : (FT)1;
+    dp = ((FT)6 * T[(size_t)j * nx + i] - sub * dp) * riv[j];
+    C0[(long)j * pt] = dp;
+  }
+  FT out = dp;
+  for (int j = nv - 2; j >= 0; --j) {
+    out = C0[(long)j * pt] - cpv[j] * out;
+    C0[(long)j * pt] = out;
+  }
+  C0[-pt] = C0[pt];
+  C0[(long)nv * pt] = C0[(long)(nv - 2) * pt];
+}
+
+// Mirror ghost columns c(-1, j) = c(1, j), c(nx, j) = c(nx - 2, j) for
+// j in [-1, nv] (corners follow from the ghost rows).
+template <typename FT>
+__global__ __launch_bounds__(256) void k_ghost_x(KP p, FT *__restrict__ C) {
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x) - 1;
+  if (j > p.nv) return;
+  const long pt = p.pitch;
+  FT *row = C + (long)(j + PV) * pt + PX;
+  row[-1] = row[1];
+  row[p.nx] = row[p.nx - 2];
+}
+
+// Rows [j0, j0 + nrows) of f0 (double, src holds those rows) -> F (padded
+// interior), the outermost ring zeroed.
+template <typename FT>
+__global__ __launch_bounds__(256) void k_load_f0(KP p,
+                                                 const double *__restrict__ src,
+                                                 int j0, int nrows,
+                                                 FT *__restrict__ F) {
+  const long long n = (long long)p.nx * nrows;
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += gsz) {
+    const int jr = (int)(q / p.nx), i = (int)(q - (long long)jr * p.nx);
+    const int j = j0 + jr;
+    const bool ring = (i == 0 || j == 0 || i == p.nx - 1 || j == p.nv - 1);
+    F[(long)(j + PV) * p.pitch + (i + PX)] = ring ? (FT)0 : (FT)src[q];
+  }
+}
+
+}  // namespace vpk

@@ -1,0 +1,62 @@
+"""The C-ABI library loads, exports every entry point include/vp.h declares,
+and validates parameters on the host (no device work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vp.h")).read()
+    return sorted(set(re.findall(r"\b(vp_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def vp():
+    import paper_1705_03750_amd as vp
+    if not os.path.exists(vp.LIB_PATH):
+        from paper_1705_03750_amd import build
+        build.build()
+    return vp
+
+
+def test_exports_every_declared_symbol(vp):
+    L = C.CDLL(vp.LIB_PATH)
+    names = _declared()
+    assert "vp_step" in names and "vp_reconstruct_f" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(vp.EXPORTS) == set(names)
+
+
+def test_footprint_and_validation(vp):
+    n_fp64 = vp.footprint(nx=256, sx=4, dt=1e-3)
+    n_mixed = vp.footprint(nx=256, sx=4, dt=1e-3, precision="mixed")
+    assert n_fp64 > n_mixed > 0
+    big = vp.footprint(nx=2048, sx=8, dt=5e-4)
+    assert 3 * 2048 * 2048 * 8 < big < 8 * 2048 * 2048 * 8
+    for bad in (dict(nx=250, sx=4, dt=1e-3),      # nx % sx
+                dict(nx=4, sx=1, dt=1e-3),        # too small
+                dict(nx=64, sx=4, dt=0.0),        # dt <= 0
+                dict(nx=64, sx=4, dt=1e-3, x_min=1.0, x_max=1.0),
+                dict(nx=64, sx=4, dt=1e-3, n_s=-1),
+                dict(nx=64, sx=4, dt=1e-3, precision=7)):
+        with pytest.raises(vp.VPError) as ei:
+            vp.footprint(**bad)
+        assert ei.value.code == vp.EINVAL
+
+
+def test_create_rejects_small_or_null_workspace(vp):
+    p = vp.make_params(nx=64, sx=4, dt=1e-3)
+    n = C.c_size_t(0)
+    assert vp.lib().vp_footprint(C.byref(p), C.byref(n)) == 0
+    h = C.c_void_p()
+    # null workspace and short workspace are refused before any device work
+    assert vp.lib().vp_create(C.byref(p), None, n.value, None,
+                              C.byref(h)) == vp.EINVAL
+    assert vp.lib().vp_create(C.byref(p), C.c_void_p(256), n.value - 1, None,
+                              C.byref(h)) == vp.ENOMEM
+    assert b"vp_footprint" in vp.lib().vp_last_error(None)
