@@ -102,6 +102,71 @@ def cpu_baseline(cfg, f0, steps: int, threads: int):
                       f"{dt:.2f} s wall"}
 
 
+def serve_leg(count: int, step_scale: float, seed: int, occupancy: float,
+              max_active: int, pool_gb: float):
+    """Continuous-batching leg: `count` independent mixed-precision runs drawn
+    from the serving mix (N in {256, 512, 1024, 2048}, element stride 4 or 8,
+    steps ~ U{200..2000} times step_scale, remap every 25-50 steps, 1-6
+    seeded halos), first all at t = 0 to measure device time per site
+    update, then arriving as a Poisson process at the rate that targets the
+    requested device occupancy.  Reports p50/p99 latency (arrival to final f
+    on the device) and aggregate site updates/s."""
+    import numpy as np
+    import torch
+    import paper_1705_03750_amd as vp
+    import workloads as W
+    mix = W.serving_requests(count, sizes=(256, 512, 1024, 2048),
+                             strides=(4, 8), steps=(200, 2000), remap=(25, 50))
+    reqs = []
+    for cfg, k in mix:
+        nsteps = max(1, int(round(cfg.steps * step_scale)))
+        f0 = W.request_f0(cfg, k)
+        reqs.append(dict(
+            params=dict(nx=cfg.n, sx=cfg.s, dt=cfg.dt, n_s=cfg.n_s,
+                        precision="mixed"),
+            f0=torch.as_tensor(f0, device="cuda:0"),
+            out=torch.empty((cfg.n, cfg.n), dtype=torch.float32,
+                            device="cuda:0"),
+            nsteps=nsteps, tag=int(cfg.seed), arrival_s=0.0))
+    work = np.array([r["params"]["nx"] ** 2 * r["nsteps"] for r in reqs],
+                    dtype=np.float64)
+    srv = vp.Server(precision="mixed", max_active=max_active,
+                    pool_bytes=int(pool_gb * (1 << 30)))
+    torch.cuda.synchronize()
+    _, cal = srv.run(reqs)                       # full load, all at t = 0
+    cost = cal["gpu_busy_s"] / cal["site_updates"]
+    mean_service = cost * work.mean()
+    lam = occupancy / mean_service
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+    t -= t[0]
+    for r, a in zip(reqs, t):
+        r["arrival_s"] = float(a)
+    res, st = srv.run(reqs)
+    torch.cuda.synchronize()
+    lat = np.array([x["done_s"] - x["arrival_s"] for x in res])
+    wait = np.array([x["admit_s"] - x["arrival_s"] for x in res])
+    srv.close()
+    return {
+        "requests": len(reqs),
+        "mix": "N in {256,512,1024,2048}, stride 4 or 8, steps "
+               f"U{{200..2000}} x {step_scale}, remap every 25-50, 1-6 halos, "
+               "mixed precision",
+        "arrival_rate_per_s": lam,
+        "target_occupancy": occupancy,
+        "occupancy": st["gpu_busy_s"] / st["wall_s"] if st["wall_s"] else None,
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "p50_queue_wait_s": float(np.percentile(wait, 50)),
+        "site_updates_per_s": st["site_updates"] / st["wall_s"],
+        "full_load_site_updates_per_s": cal["site_updates"] / cal["wall_s"],
+        "max_active": st["max_active"],
+        "ticks": st["ticks"],
+        "graph_replay": bool(st["graph_replay"]),
+        "wall_s": st["wall_s"],
+    }
+
+
 def load_traffic(kind: str, precision: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     when it was taken on the current kernel source."""
@@ -125,6 +190,10 @@ def main():
                     default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-step-scale", type=float, default=0.1)
+    ap.add_argument("--serve-occupancy", type=float, default=0.8)
+    ap.add_argument("--serve", action="store_true")
     ap.add_argument("--copy-cal", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (5x), "
                          "the reference for scaling rocprofv3 FETCH_SIZE / "
@@ -202,6 +271,13 @@ def main():
                        "mixed_over_fp64": m["value"] / f["value"]}
     out["kernels_ms_per_step"] = {
         k: v[0] / args.steps for k, v in m["kernels"].items() if v[1]}
+    if args.serve:
+        out["serving"] = serve_leg(args.serve_requests, args.serve_step_scale,
+                                   seed=4, occupancy=args.serve_occupancy,
+                                   max_active=64, pool_gb=8.0)
+        print(f"[bench] serving: p50 {out['serving']['p50_latency_s']:.3f} s,"
+              f" p99 {out['serving']['p99_latency_s']:.3f} s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, f0, args.cpu_steps,
                                            args.cpu_threads)

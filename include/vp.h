@@ -174,6 +174,65 @@ int vp_time(vp_ctx *ctx, double *t, int64_t *step);
 int vp_prof_begin(vp_ctx *ctx, int max_launches);
 int vp_prof_end(vp_ctx *ctx, double *ms_host, int64_t *n_host);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of independent runs (different grids, element
+ * strides, step counts) on one device.  Requests arrive over time; a request
+ * is admitted (FIFO) as soon as a run slot is free and its vp_footprint fits
+ * in the unused part of the server's device pool; its state (F_ini, spline,
+ * elements) stays resident until it completes.  Every tick advances all
+ * admitted runs by one step with one fixed sequence of batched launches
+ * (captured once as a HIP graph and replayed); a run's arithmetic is the
+ * same as a run alone (vp_step, then vp_reconstruct_f with the transport
+ * scheme), so its output is bitwise the same alone or in any mix. */
+typedef struct vp_server vp_server;
+
+typedef struct vp_request {
+  vp_params params;     /* precision must equal the server's */
+  const double *f0_dev; /* nv*nx device doubles; read when admitted */
+  void *f_out_dev;      /* nv*nx device values (float in VP_MIXED): f after
+                           nsteps (transport reconstruction) */
+  int32_t nsteps;       /* >= 1 */
+  int32_t pad;
+  int64_t tag;
+  double arrival_s;     /* seconds after vp_server_run starts; ascending */
+} vp_request;
+
+typedef struct vp_request_result {
+  int64_t tag;
+  double arrival_s, admit_s, done_s; /* seconds after the start */
+  int32_t status;                    /* VP_OK, or the admission error */
+  int32_t pad;
+} vp_request_result;
+
+typedef struct vp_server_stats {
+  double wall_s;        /* first arrival to last completion */
+  double gpu_busy_s;    /* device time of all ticks (HIP events) */
+  int64_t ticks, site_updates, admitted, completed;
+  int32_t max_active;   /* most runs resident at once */
+  int32_t graph_replay; /* 1 when ticks ran as HIP graph replays */
+} vp_server_stats;
+
+/* Device bytes the server keeps at the head of its pool for run and work
+ * tables (the rest holds the runs' workspaces). */
+int vp_server_footprint(int precision, size_t *bytes);
+
+/* Server over caller-owned device memory dev_pool (pool_bytes > the
+ * footprint above), at most max_active (1..128) resident runs, all of one
+ * precision.  hip_stream: the caller's stream, ordered before and after
+ * each vp_server_run (the server runs on a stream of its own). */
+int vp_server_create(int precision, int max_active, void *dev_pool,
+                     size_t pool_bytes, void *hip_stream, vp_server **out);
+
+/* Serve n requests (ascending arrival_s) to completion, in real time:
+ * requests become eligible at their arrival time, are admitted as memory
+ * and slots free up, and complete when their last step's results are on
+ * the device.  res[i] describes reqs[i].  Returns when all are done. */
+int vp_server_run(vp_server *srv, const vp_request *reqs, int n,
+                  vp_request_result *res, vp_server_stats *stats);
+
+int vp_server_destroy(vp_server *srv);
+const char *vp_server_last_error(vp_server *srv);
+
 /* Wait for the stream; report a pending device-side VP_ENUMERIC. */
 int vp_sync(vp_ctx *ctx);
 

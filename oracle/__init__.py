@@ -138,8 +138,10 @@ class Oracle:
 
     def __init__(self, **p):
         self.p = dict(p)
-        self.nx, self.nv = int(p["nx"]), int(p["nv"])
-        self.sx, self.sv = int(p["sx"]), int(p["sv"])
+        self.nx = int(p["nx"])
+        self.nv = int(p.get("nv") or self.nx)
+        self.sx = int(p["sx"])
+        self.sv = int(p.get("sv") or self.sx)
         self.mx, self.mv = self.nx // self.sx, self.nv // self.sv
         self.E = self.mx * self.mv
         ext = p.get("ext", (0.0, 0.0, 0.0))

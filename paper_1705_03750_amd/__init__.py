@@ -28,7 +28,8 @@ EXPORTS = (
     "vp_step", "vp_remap", "vp_reconstruct_f", "vp_density", "vp_poisson",
     "vp_diagnostics", "vp_get_elements", "vp_set_elements",
     "vp_get_assignment", "vp_time", "vp_sync", "vp_last_error",
-    "vp_prof_begin", "vp_prof_end",
+    "vp_prof_begin", "vp_prof_end", "vp_server_footprint", "vp_server_create",
+    "vp_server_run", "vp_server_destroy", "vp_server_last_error",
 )
 PROF_KINDS = ("predict", "recon", "field", "kick", "remap_eval", "spline_fit",
               "reset", "other")
@@ -52,6 +53,26 @@ class Diag(C.Structure):
                 ("entropy", C.c_double), ("max_det_dev", C.c_double),
                 ("t", C.c_double), ("step", C.c_int64),
                 ("overflow_blocks", C.c_int64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("params", Params), ("f0_dev", C.c_void_p),
+                ("f_out_dev", C.c_void_p), ("nsteps", C.c_int32),
+                ("pad", C.c_int32), ("tag", C.c_int64),
+                ("arrival_s", C.c_double)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("arrival_s", C.c_double),
+                ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("wall_s", C.c_double), ("gpu_busy_s", C.c_double),
+                ("ticks", C.c_int64), ("site_updates", C.c_int64),
+                ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("max_active", C.c_int32), ("graph_replay", C.c_int32)]
 
 
 class VPError(RuntimeError):
@@ -91,6 +112,13 @@ def lib():
             "vp_sync": [vp],
             "vp_prof_begin": [vp, C.c_int],
             "vp_prof_end": [vp, pd, C.POINTER(C.c_int64)],
+            "vp_server_footprint": [C.c_int, C.POINTER(C.c_size_t)],
+            "vp_server_create": [C.c_int, C.c_int, vp, C.c_size_t, vp,
+                                 C.POINTER(vp)],
+            "vp_server_run": [vp, C.POINTER(Request), C.c_int,
+                              C.POINTER(RequestResult),
+                              C.POINTER(ServerStats)],
+            "vp_server_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -98,6 +126,8 @@ def lib():
             fn.restype = C.c_int
         L.vp_last_error.argtypes = [vp]
         L.vp_last_error.restype = C.c_char_p
+        L.vp_server_last_error.argtypes = [vp]
+        L.vp_server_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -262,3 +292,60 @@ class VlasovRun:
     def sync(self):
         self._chk(lib().vp_sync(self.h), self.h)
         self._keep = []
+
+
+class Server:
+    """Continuous-batching server (vp_server_* in include/vp.h) over one
+    device pool (a torch uint8 tensor of pool_bytes)."""
+
+    def __init__(self, precision="mixed", max_active=64, pool_bytes=1 << 31,
+                 device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+        self.device = torch.device(device)
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8,
+                                device=self.device)
+        stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = lib().vp_server_create(self.precision, int(max_active),
+                                    C.c_void_p(self.pool.data_ptr()),
+                                    int(pool_bytes),
+                                    C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc:
+            raise VPError(rc, lib().vp_server_last_error(None).decode())
+        self.h = h
+
+    def run(self, requests):
+        """requests: list of dicts with params (make_params kwargs), f0
+        (device float64 tensor), out (device tensor), nsteps, tag, arrival_s
+        (ascending).  Returns (results list of dicts, stats dict)."""
+        n = len(requests)
+        arr = (Request * max(n, 1))()
+        for i, r in enumerate(requests):
+            arr[i].params = make_params(**r["params"])
+            arr[i].f0_dev = r["f0"].data_ptr()
+            arr[i].f_out_dev = r["out"].data_ptr()
+            arr[i].nsteps = int(r["nsteps"])
+            arr[i].tag = int(r.get("tag", i))
+            arr[i].arrival_s = float(r.get("arrival_s", 0.0))
+        res = (RequestResult * max(n, 1))()
+        st = ServerStats()
+        rc = lib().vp_server_run(self.h, arr, n, res, C.byref(st))
+        if rc:
+            raise VPError(rc, lib().vp_server_last_error(self.h).decode())
+        out = [{k: getattr(res[i], k) for k, _ in RequestResult._fields_
+                if k != "pad"} for i in range(n)]
+        stats = {k: getattr(st, k) for k, _ in ServerStats._fields_}
+        return out, stats
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

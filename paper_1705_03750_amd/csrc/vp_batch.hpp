@@ -1,0 +1,193 @@
+// vp_batch.hpp -- batched kernels of the serving loop: one launch advances
+// many independent runs (different grids, element strides and step counts).
+//
+// Every kernel has a fixed grid and walks a per-phase work table: item ids
+// [0, total) are split among the runs of the phase (table entry = run slot,
+// first item, per-run argument).  A workgroup finds its run by a uniform
+// binary search, then calls exactly the same per-tile device routine as the
+// single-run kernels, so a run's arithmetic does not depend on its
+// batch-mates and its results are bitwise those of a run alone.  Because the
+// grids are fixed and all variability lives in device tables, the sequence
+// of launches of one tick is captured once in a HIP graph and replayed.
+#pragma once
+
+#include "vp_kernels.hpp"
+
+namespace vpk {
+
+constexpr int MAXR = 128;  // run slots of one server
+
+struct PhaseItem {
+  int slot, begin, arg, pad;
+};
+struct PhaseTable {
+  int n, total, pad0, pad1;
+  PhaseItem it[MAXR];
+};
+
+// Phases of one tick, in launch order.
+enum {
+  PH_PRED = 0,    // predictor drift + records + block lists (first step)
+  PH_RECON,       // reconstruction + column sums + force
+  PH_KICK,        // kick + corrector (+ next predictor when continuing)
+  PH_RM_PRED,     // remap: records + lists of the post-corrector elements
+  PH_RM_EVAL,     // remap evaluation into F_ini
+  PH_FIT_X,       // spline fit along x
+  PH_FIT_V,       // spline fit along v
+  PH_GHOST,       // mirror ghost columns
+  PH_RESET,       // new isotropic elements, counts cleared
+  PH_FIN_PRED,    // final reconstruction: records + lists
+  PH_FIN_RECON,   // final reconstruction into the request's output
+  PH_FIN_ZERO,    // counts cleared after the final reconstruction
+  NPH
+};
+
+// Element-pass argument bits.
+enum {
+  EA_KICK = 1, EA_DRIFT = 2, EA_PRED = 4, EA_REG = 8, EA_REGBUF1 = 16,
+  EA_ZERO = 32, EA_ZEROBUF1 = 64, EA_RESET = 128
+};
+
+template <typename FT>
+struct RunDesc {
+  KP k;
+  long long nb;
+  double *st, *rec, *qm, *part, *S, *Mw, *Ml, *acc, *dpart;
+  int *cnt, *lst, *flags, *colcnt;
+  unsigned long long *ovf;
+  FT *F, *C, *T;
+  const FT *tab;
+  FT *fout;
+};
+
+__device__ __forceinline__ int find_run(const PhaseTable *__restrict__ t,
+                                        int item) {
+  int lo = 0, hi = t->n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t->it[mid].begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Element passes (predict / kick / remap records / reset / count clearing):
+// 256 elements and 256 block counts per item.
+template <typename FT>
+__global__ __launch_bounds__(256) void kb_elem(
+    const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int q = find_run(tab, item);
+    const PhaseItem pi = tab->it[q];
+    const RunDesc<FT> &R = runs[pi.slot];
+    const KP &p = R.k;
+    const int arg = pi.arg;
+    const long long idx = (long long)(item - pi.begin) * 256 + threadIdx.x;
+    if (arg & EA_ZERO) {
+      int *cz = R.cnt + ((arg & EA_ZEROBUF1) ? R.nb : 0);
+      if (idx < R.nb) cz[idx] = 0;
+    }
+    if (idx >= p.E) continue;
+    const int e = (int)idx;
+    const size_t E = (size_t)p.E;
+    if (arg & EA_RESET) {
+      const int k = e % p.mx, l = e / p.mx;
+      for (int s = 0; s < NSTATE; ++s) R.st[s * E + e] = 0.0;
+      R.st[S_X * E + e] = site_x(p, p.sx * k + p.sx / 2);
+      R.st[S_V * E + e] = site_v(p, p.sv * l + p.sv / 2);
+      R.st[S_TXX * E + e] = 1.0;
+      R.st[S_TVV * E + e] = 1.0;
+      continue;
+    }
+    const bool kick = arg & EA_KICK, drift = arg & EA_DRIFT,
+               pred = arg & EA_PRED;
+    if (!kick && !pred) continue;
+    ElemState s;
+    elem_load(R.st, E, e, s);
+    if (kick) elem_kick(p, R.acc, s);
+    if (pred && drift) elem_drift(p, s);
+    if (kick || (pred && drift)) elem_store(R.st, E, e, s);
+    if (pred)
+      elem_record(p, s, e, R.rec, R.qm,
+                  R.cnt + ((arg & EA_REGBUF1) ? R.nb : 0), R.lst, R.flags,
+                  (arg & EA_REG) ? 1 : 0);
+  }
+}
+
+// Reconstruction tiles (8 columns x 64 rows per item); arg = live count
+// buffer.  MODE_DENSITY also computes the force; MODE_F writes R.fout.
+template <typename FT, int MODE>
+__global__ __launch_bounds__(512) void kb_recon(
+    const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    __syncthreads();
+    const int q = find_run(tab, item);
+    const PhaseItem pi = tab->it[q];
+    const RunDesc<FT> &R = runs[pi.slot];
+    const int local = item - pi.begin;
+    const int bx = local % R.k.nbx, gy = local / R.k.nbx;
+    recon_tile<FT, MODE>(R.k, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
+                         R.flags, R.F, R.part, R.colcnt, R.S, R.fout, nullptr,
+                         R.dpart, R.ovf, R.colcnt + R.k.nbx, R.Mw, R.Ml, R.acc,
+                         nullptr, bx, gy);
+  }
+}
+
+template <typename FT>
+__global__ __launch_bounds__(512) void kb_remap(
+    const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int q = find_run(tab, item);
+    const PhaseItem pi = tab->it[q];
+    const RunDesc<FT> &R = runs[pi.slot];
+    const int local = item - pi.begin;
+    const int bx = local % R.k.nbx, gy = local / R.k.nbx;
+    remap_tile<FT, 0>(R.k, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
+                      R.flags, R.C, R.F, R.ovf, bx, gy);
+  }
+}
+
+template <typename FT>
+__global__ __launch_bounds__(64) void kb_fit_x(
+    const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    __syncthreads();
+    const int q = find_run(tab, item);
+    const PhaseItem pi = tab->it[q];
+    const RunDesc<FT> &R = runs[pi.slot];
+    const KP &p = R.k;
+    fit_x_rows<FT>(p, R.F, R.T, R.tab, R.tab + p.nx, item - pi.begin);
+  }
+}
+
+template <typename FT>
+__global__ __launch_bounds__(64) void kb_fit_v(
+    const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int q = find_run(tab, item);
+    const PhaseItem pi = tab->it[q];
+    const RunDesc<FT> &R = runs[pi.slot];
+    const KP &p = R.k;
+    fit_v_cols<FT>(p, R.T, R.C, R.tab + 2 * p.nx, R.tab + 2 * p.nx + p.nv,
+                   item - pi.begin);
+  }
+}
+
+template <typename FT>
+__global__ __launch_bounds__(256) void kb_ghost(
+    const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int q = find_run(tab, item);
+    const PhaseItem pi = tab->it[q];
+    const RunDesc<FT> &R = runs[pi.slot];
+    ghost_x_rows<FT>(R.k, R.C, item - pi.begin);
+  }
+}
+
+}  // namespace vpk

@@ -19,7 +19,12 @@
 #include <vector>
 
 #include "vp.h"
+#include "vp_batch.hpp"
 #include "vp_kernels.hpp"
+
+#include <chrono>
+#include <map>
+#include <thread>
 
 using namespace vpk;
 
@@ -28,7 +33,7 @@ namespace {
 thread_local std::string g_create_error;
 
 struct Layout {
-  size_t F, C, T, st, rec, cnt, lst, flags, ovf, part, colcnt, S, Mw, Ml, acc,
+  size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, colcnt, S, Mw, Ml, acc,
       dpart, dout, tab, total;
   size_t fbytes;  // bytes per f value
   long long nb;
@@ -117,6 +122,7 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.T = take(N2 * fb);
   L.st = take((size_t)NSTATE * k.E * 8);
   L.rec = take((size_t)RS * k.E * 8);
+  L.qm = take((size_t)2 * k.E * 8);
   L.cnt = take((size_t)2 * L.nb * 4);  // two count buffers, see vp_ctx::cur
   L.lst = take((size_t)L.nb * k.cap * 4);
   L.flags = take(64);
@@ -152,6 +158,7 @@ struct vp_ctx {
   bool ready;
   int cur = 0;  // which of the two block-count buffers holds the live lists
   std::string err;
+  std::vector<char> host_tab;  // source of the pivot-table upload
   // profiling: event pairs per kernel kind
   bool prof = false;
   int prof_cap = 0;
@@ -187,12 +194,12 @@ struct ProfScope {
   ProfScope(vp_ctx *c_, int k) : c(c_), kind(k), on(false) {
     if (c->prof && c->ev_used[kind] < c->prof_cap) {
       on = true;
-      hipEventRecord(c->ev[kind][2 * c->ev_used[kind]], c->stream);
+      (void)hipEventRecord(c->ev[kind][2 * c->ev_used[kind]], c->stream);
     }
   }
   ~ProfScope() {
     if (on) {
-      hipEventRecord(c->ev[kind][2 * c->ev_used[kind] + 1], c->stream);
+      (void)hipEventRecord(c->ev[kind][2 * c->ev_used[kind] + 1], c->stream);
       c->ev_used[kind] += 1;
     }
   }
@@ -217,7 +224,7 @@ int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
       std::max<long long>(k.E, std::min<long long>(nbz, 1 << 22));
   hipLaunchKernelGGL(k_elem, dim3(grid_for(n, 256)), dim3(256), 0, c->stream,
                      k, c->at<double>(c->L.st), c->at<double>(c->L.acc),
-                     c->at<double>(c->L.rec),
+                     c->at<double>(c->L.rec), c->at<double>(c->L.qm),
                      zero_buf >= 0 ? c->counts(zero_buf) : nullptr, nbz,
                      c->counts(reg_buf), c->at<int>(c->L.lst),
                      c->at<int>(c->L.flags), kick, drift, predict, reg);
@@ -242,10 +249,11 @@ template <typename FT, int MODE>
 int launch_recon(vp_ctx *c, void *fout, int *aout, double *rho_out) {
   const KP &k = c->k;
   ProfScope ps(c, PK_RECON);
-  hipLaunchKernelGGL((k_recon<FT, MODE>), dim3(c->L.nwg_x, c->L.nwg_y),
+  hipLaunchKernelGGL((k_recon<FT, MODE>), dim3(c->L.nwg_x * c->L.nwg_y),
                      dim3(512), 0, c->stream, k, c->at<double>(c->L.rec),
-                     c->counts(c->cur), c->at<int>(c->L.lst),
-                     c->at<int>(c->L.flags), c->at<FT>(c->L.F),
+                     c->at<double>(c->L.qm), c->counts(c->cur),
+                     c->at<int>(c->L.lst), c->at<int>(c->L.flags),
+                     c->at<FT>(c->L.F),
                      c->at<double>(c->L.part), c->at<int>(c->L.colcnt),
                      c->at<double>(c->L.S), reinterpret_cast<FT *>(fout), aout,
                      c->at<double>(c->L.dpart),
@@ -268,7 +276,7 @@ int launch_field(vp_ctx *c, const double *in, int in_is_rho, double *rho_out,
                  double *a_out, double *da_out, double *d2a_out) {
   ProfScope ps(c, PK_FIELD);
   hipLaunchKernelGGL(k_field, dim3(1), dim3(1024), 0, c->stream, c->k, in,
-                     in_is_rho, c->at<double>(c->L.Mw), c->at<double>(c->L.Ml),
+                     in_is_rho, c->at<double>(c->L.Ml),
                      c->at<double>(c->L.acc), rho_out, a_out, da_out, d2a_out);
   VP_LAUNCH_CHECK(c, "k_field");
   return VP_OK;
@@ -314,10 +322,12 @@ template <typename FT, int TO_F>
 int launch_remap_t(vp_ctx *c, void *fout) {
   ProfScope ps(c, PK_REMAP);
   FT *out = TO_F ? reinterpret_cast<FT *>(fout) : c->at<FT>(c->L.F);
-  hipLaunchKernelGGL((k_remap_eval<FT, TO_F>), dim3(c->L.nwg_x, c->L.nwg_y),
+  hipLaunchKernelGGL((k_remap_eval<FT, TO_F>),
+                     dim3(c->L.nwg_x * c->L.nwg_y),
                      dim3(512), 0, c->stream, c->k, c->at<double>(c->L.rec),
-                     c->counts(c->cur), c->at<int>(c->L.lst),
-                     c->at<int>(c->L.flags), c->at<FT>(c->L.C), out,
+                     c->at<double>(c->L.qm), c->counts(c->cur),
+                     c->at<int>(c->L.lst), c->at<int>(c->L.flags),
+                     c->at<FT>(c->L.C), out,
                      c->at<unsigned long long>(c->L.ovf));
   VP_LAUNCH_CHECK(c, "k_remap_eval");
   return VP_OK;
@@ -390,11 +400,12 @@ int upload_tables(vp_ctx *c) {
   all.insert(all.end(), rix.begin(), rix.end());
   all.insert(all.end(), cpv.begin(), cpv.end());
   all.insert(all.end(), riv.begin(), riv.end());
-  hipError_t e = hipMemcpyAsync(c->at<FT>(c->L.tab), all.data(),
-                                all.size() * sizeof(FT), hipMemcpyHostToDevice,
+  // the host copy lives as long as the context, so no wait is needed
+  c->host_tab.assign(reinterpret_cast<const char *>(all.data()),
+                     reinterpret_cast<const char *>(all.data() + all.size()));
+  hipError_t e = hipMemcpyAsync(c->at<FT>(c->L.tab), c->host_tab.data(),
+                                c->host_tab.size(), hipMemcpyHostToDevice,
                                 c->stream);
-  if (e != hipSuccess) return dev_fail(c, e, "table upload");
-  e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return dev_fail(c, e, "table upload");
   return VP_OK;
 }
@@ -675,7 +686,7 @@ int vp_prof_end(vp_ctx *c, double *ms, int64_t *n) {
     if (ms) ms[k] = tot;
     if (n) n[k] = c->ev_used[k];
     for (auto &e : c->ev[k])
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
     c->ev[k].clear();
     c->ev_used[k] = 0;
   }
@@ -693,6 +704,545 @@ int vp_sync(vp_ctx *c) {
 const char *vp_last_error(vp_ctx *c) {
   if (!c) return g_create_error.c_str();
   return c->err.c_str();
+}
+
+}  // extern "C"
+
+// ================================================================ serving
+
+namespace {
+
+// First-fit allocator over the server pool (256-byte granules).
+class PoolAlloc {
+ public:
+  void init(size_t base, size_t size) {
+    free_.clear();
+    if (size) free_[base] = size;
+  }
+  bool alloc(size_t bytes, size_t &off) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        off = it->first;
+        const size_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+struct Slot {
+  bool used = false;
+  vp_ctx *c = nullptr;
+  int req = -1;
+  int nsteps = 0, done = 0;
+  bool need_predict = true;
+  size_t off = 0, bytes = 0;
+};
+
+constexpr int RING = 8;          // host work-table buffers in flight
+constexpr int MAX_INFLIGHT = 3;  // ticks enqueued ahead of the device
+constexpr int GRID_TILE = 2048;  // fixed grids of the batched kernels
+constexpr int GRID_ELEM = 2048;
+constexpr int GRID_FIT = 1024;
+
+size_t header_bytes(int precision) {
+  const size_t rd = precision == VP_MIXED ? sizeof(RunDesc<float>)
+                                          : sizeof(RunDesc<double>);
+  return align_up(MAXR * rd) + align_up(NPH * sizeof(PhaseTable));
+}
+
+}  // namespace
+
+struct vp_server {
+  int precision = VP_FP64;
+  int max_active = 1;
+  hipStream_t caller = nullptr, stream = nullptr;
+  char *pool = nullptr;
+  size_t pool_bytes = 0;
+  void *runs_dev = nullptr;
+  PhaseTable *tabs_dev = nullptr;
+  std::vector<char> runs_host;  // RunDesc mirror, one per slot
+  PhaseTable *ring = nullptr;   // pinned host [RING][NPH]
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = false;
+  PoolAlloc alloc;
+  Slot slot[MAXR];
+  std::string err;
+
+  size_t rd_size() const {
+    return precision == VP_MIXED ? sizeof(RunDesc<float>)
+                                 : sizeof(RunDesc<double>);
+  }
+};
+
+namespace {
+
+int srv_fail(vp_server *s, hipError_t e, const char *where) {
+  s->err = std::string(where) + ": " + hipGetErrorString(e);
+  return VP_EDEVICE;
+}
+
+template <typename FT>
+void launch_tick_kernels(vp_server *s) {
+  const RunDesc<FT> *runs = reinterpret_cast<const RunDesc<FT> *>(s->runs_dev);
+  const PhaseTable *t = s->tabs_dev;
+  hipStream_t st = s->stream;
+  hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
+                     t + PH_PRED);
+  hipLaunchKernelGGL((kb_recon<FT, MODE_DENSITY>), dim3(GRID_TILE), dim3(512),
+                     0, st, runs, t + PH_RECON);
+  hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
+                     t + PH_KICK);
+  hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
+                     t + PH_RM_PRED);
+  hipLaunchKernelGGL(kb_remap<FT>, dim3(GRID_TILE), dim3(512), 0, st, runs,
+                     t + PH_RM_EVAL);
+  hipLaunchKernelGGL(kb_fit_x<FT>, dim3(GRID_FIT), dim3(64), 0, st, runs,
+                     t + PH_FIT_X);
+  hipLaunchKernelGGL(kb_fit_v<FT>, dim3(GRID_FIT), dim3(64), 0, st, runs,
+                     t + PH_FIT_V);
+  hipLaunchKernelGGL(kb_ghost<FT>, dim3(GRID_FIT), dim3(256), 0, st, runs,
+                     t + PH_GHOST);
+  hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
+                     t + PH_RESET);
+  hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
+                     t + PH_FIN_PRED);
+  hipLaunchKernelGGL((kb_recon<FT, MODE_F>), dim3(GRID_TILE), dim3(512), 0, st,
+                     runs, t + PH_FIN_RECON);
+  hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
+                     t + PH_FIN_ZERO);
+}
+
+void tick_kernels(vp_server *s) {
+  if (s->precision == VP_MIXED)
+    launch_tick_kernels<float>(s);
+  else
+    launch_tick_kernels<double>(s);
+}
+
+template <typename FT>
+void fill_desc(vp_ctx *c, void *fout, void *dst) {
+  RunDesc<FT> d{};
+  d.k = c->k;
+  d.nb = c->L.nb;
+  d.st = c->at<double>(c->L.st);
+  d.rec = c->at<double>(c->L.rec);
+  d.qm = c->at<double>(c->L.qm);
+  d.part = c->at<double>(c->L.part);
+  d.S = c->at<double>(c->L.S);
+  d.Mw = c->at<double>(c->L.Mw);
+  d.Ml = c->at<double>(c->L.Ml);
+  d.acc = c->at<double>(c->L.acc);
+  d.dpart = c->at<double>(c->L.dpart);
+  d.cnt = c->counts(0);
+  d.lst = c->at<int>(c->L.lst);
+  d.flags = c->at<int>(c->L.flags);
+  d.colcnt = c->at<int>(c->L.colcnt);
+  d.ovf = c->at<unsigned long long>(c->L.ovf);
+  d.F = c->at<FT>(c->L.F);
+  d.C = c->at<FT>(c->L.C);
+  d.T = c->at<FT>(c->L.T);
+  d.tab = c->at<FT>(c->L.tab);
+  d.fout = reinterpret_cast<FT *>(fout);
+  std::memcpy(dst, &d, sizeof(d));
+}
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Work tables of one tick for every resident run, in slot order.  Returns
+// the slots that finish with this tick.  Advances the host mirror of each
+// run (step count, live count buffer, pending predictor).
+void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
+  for (int ph = 0; ph < NPH; ++ph) {
+    tab[ph].n = 0;
+    tab[ph].total = 0;
+  }
+  auto add = [&](int ph, int slot, int items, int arg) {
+    PhaseTable &t = tab[ph];
+    if (items <= 0) return;
+    t.it[t.n].slot = slot;
+    t.it[t.n].begin = t.total;
+    t.it[t.n].arg = arg;
+    t.n += 1;
+    t.total += items;
+  };
+  finishing.clear();
+  for (int q = 0; q < s->max_active; ++q) {
+    Slot &sl = s->slot[q];
+    if (!sl.used || sl.done >= sl.nsteps) continue;
+    vp_ctx *c = sl.c;
+    const KP &k = c->k;
+    const int cur = c->cur;
+    const int el_items = ceil_div(k.E, 256);
+    const int elz_items = ceil_div(std::max<long long>(k.E, c->L.nb), 256);
+    const int tiles = k.nbx * k.ngy;
+    const int regb = cur ? EA_REGBUF1 : 0, zb = cur ? EA_ZEROBUF1 : 0;
+    if (sl.need_predict)
+      add(PH_PRED, q, el_items, EA_PRED | EA_DRIFT | EA_REG | regb);
+    add(PH_RECON, q, tiles, cur);
+    const int step_after = sl.done + 1;
+    const bool remap_due = c->p.n_s > 0 && step_after % c->p.n_s == 0;
+    const bool finish = step_after == sl.nsteps;
+    if (!remap_due && !finish) {
+      add(PH_KICK, q, elz_items,
+          EA_KICK | EA_DRIFT | EA_PRED | EA_REG | (cur ? 0 : EA_REGBUF1) |
+              EA_ZERO | zb);
+      c->cur ^= 1;
+      sl.need_predict = false;
+    } else {
+      add(PH_KICK, q, elz_items, EA_KICK | EA_ZERO | zb);
+      sl.need_predict = true;
+    }
+    const int cr = c->cur;
+    const int regr = cr ? EA_REGBUF1 : 0, zr = cr ? EA_ZEROBUF1 : 0;
+    if (remap_due) {
+      add(PH_RM_PRED, q, el_items, EA_PRED | EA_REG | regr);
+      add(PH_RM_EVAL, q, tiles, cr);
+      add(PH_FIT_X, q, ceil_div(k.nv, 64), 0);
+      add(PH_FIT_V, q, ceil_div(k.nx, 64), 0);
+      add(PH_GHOST, q, ceil_div(k.nv + 2, 256), 0);
+      add(PH_RESET, q, elz_items, EA_RESET | EA_ZERO | zr);
+    }
+    if (finish) {
+      add(PH_FIN_PRED, q, el_items, EA_PRED | EA_REG | regr);
+      add(PH_FIN_RECON, q, tiles, cr);
+      add(PH_FIN_ZERO, q, ceil_div(c->L.nb, 256), EA_ZERO | zr);
+      finishing.push_back(q);
+    }
+    sl.done = step_after;
+    c->step = step_after;
+    c->t = (double)step_after * c->p.dt;
+  }
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+int vp_server_footprint(int precision, size_t *bytes) {
+  if (!bytes || (precision != VP_FP64 && precision != VP_MIXED))
+    return VP_EINVAL;
+  *bytes = header_bytes(precision);
+  return VP_OK;
+}
+
+int vp_server_create(int precision, int max_active, void *dev_pool,
+                     size_t pool_bytes, void *hip_stream, vp_server **out) {
+  if (!out) return VP_EINVAL;
+  *out = nullptr;
+  if ((precision != VP_FP64 && precision != VP_MIXED) || max_active < 1 ||
+      max_active > MAXR || !dev_pool ||
+      reinterpret_cast<uintptr_t>(dev_pool) % 256 != 0 ||
+      pool_bytes <= header_bytes(precision)) {
+    g_create_error = "invalid server arguments";
+    return VP_EINVAL;
+  }
+  vp_server *s = new (std::nothrow) vp_server();
+  if (!s) return VP_ENOMEM;
+  s->precision = precision;
+  s->max_active = max_active;
+  s->caller = reinterpret_cast<hipStream_t>(hip_stream);
+  s->pool = reinterpret_cast<char *>(dev_pool);
+  s->pool_bytes = pool_bytes;
+  const size_t runs_bytes = align_up(MAXR * s->rd_size());
+  s->runs_dev = s->pool;
+  s->tabs_dev = reinterpret_cast<PhaseTable *>(s->pool + runs_bytes);
+  s->runs_host.assign(MAXR * s->rd_size(), 0);
+  s->alloc.init(header_bytes(precision), pool_bytes - header_bytes(precision));
+  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&s->ring),
+                      sizeof(PhaseTable) * NPH * RING, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    g_create_error = std::string("server set-up: ") + hipGetErrorString(e);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return VP_EDEVICE;
+  }
+  std::memset(s->ring, 0, sizeof(PhaseTable) * NPH * RING);
+  // empty work tables on the device before anything runs
+  e = hipMemcpyAsync(s->tabs_dev, s->ring, sizeof(PhaseTable) * NPH,
+                     hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  // capture the launch sequence of one tick
+  if (e == hipSuccess &&
+      hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) ==
+          hipSuccess) {
+    tick_kernels(s);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s->stream, &g) == hipSuccess && g &&
+        hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0) == hipSuccess) {
+      s->graph = g;
+      s->use_graph = true;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  (void)hipGetLastError();
+  if (e != hipSuccess) {
+    g_create_error = std::string("server set-up: ") + hipGetErrorString(e);
+    (void)hipStreamDestroy(s->stream);
+    (void)hipHostFree(s->ring);
+    delete s;
+    return VP_EDEVICE;
+  }
+  *out = s;
+  return VP_OK;
+}
+
+int vp_server_destroy(vp_server *s) {
+  if (!s) return VP_EINVAL;
+  (void)hipStreamSynchronize(s->stream);
+  for (int q = 0; q < MAXR; ++q) delete s->slot[q].c;
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->ring) (void)hipHostFree(s->ring);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return VP_OK;
+}
+
+const char *vp_server_last_error(vp_server *s) {
+  return s ? s->err.c_str() : g_create_error.c_str();
+}
+
+int vp_server_run(vp_server *s, const vp_request *reqs, int n,
+                  vp_request_result *res, vp_server_stats *stats) {
+  if (!s || (n > 0 && (!reqs || !res))) return VP_EINVAL;
+  for (int i = 1; i < n; ++i)
+    if (reqs[i].arrival_s < reqs[i - 1].arrival_s) return VP_EINVAL;
+  hipError_t e;
+  // order after the caller's pending work (inputs)
+  hipEvent_t ev_in;
+  if ((e = hipEventCreateWithFlags(&ev_in, hipEventDisableTiming)) != hipSuccess)
+    return srv_fail(s, e, "event");
+  (void)hipEventRecord(ev_in, s->caller);
+  (void)hipStreamWaitEvent(s->stream, ev_in, 0);
+  // per-tick timing events
+  struct Tick {
+    hipEvent_t a, b;
+    std::vector<int> finishing;
+    int ring;
+  };
+  std::vector<hipEvent_t> evpool;
+  auto get_ev = [&]() {
+    hipEvent_t ev;
+    if (!evpool.empty()) {
+      ev = evpool.back();
+      evpool.pop_back();
+    } else if (hipEventCreate(&ev) != hipSuccess) {
+      ev = nullptr;
+    }
+    return ev;
+  };
+  std::vector<Tick> inflight;  // FIFO
+  std::vector<int> waiting;    // request ids, FIFO
+  size_t wait_head = 0;
+  int next = 0, completed = 0, active = 0, ring_pos = 0;
+  vp_server_stats st{};
+  st.graph_replay = s->use_graph ? 1 : 0;
+  for (int i = 0; i < n; ++i) {
+    res[i].tag = reqs[i].tag;
+    res[i].arrival_s = reqs[i].arrival_s;
+    res[i].admit_s = res[i].done_s = -1.0;
+    res[i].status = VP_OK;
+  }
+  const double t0 = now_s();
+  double busy = 0.0;
+  int rc = VP_OK;
+
+  auto retire = [&](Tick &tk, double tnow) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, tk.a, tk.b) == hipSuccess) busy += ms * 1e-3;
+    for (int q : tk.finishing) {
+      Slot &sl = s->slot[q];
+      res[sl.req].done_s = tnow;
+      st.site_updates += (int64_t)sl.c->k.nx * sl.c->k.nv * sl.nsteps;
+      delete sl.c;  // the device is done with it: its last tick completed
+      s->alloc.release(sl.off, sl.bytes);
+      sl = Slot();
+      active -= 1;
+      completed += 1;
+    }
+    evpool.push_back(tk.a);
+    evpool.push_back(tk.b);
+  };
+
+  while (completed < n && rc == VP_OK) {
+    double tnow = now_s() - t0;
+    while (next < n && reqs[next].arrival_s <= tnow) waiting.push_back(next++);
+    // completions
+    while (!inflight.empty() &&
+           hipEventQuery(inflight.front().b) == hipSuccess) {
+      retire(inflight.front(), now_s() - t0);
+      inflight.erase(inflight.begin());
+    }
+    // admissions, first come first served
+    while (wait_head < waiting.size()) {
+      const int r = waiting[wait_head];
+      const vp_request &rq = reqs[r];
+      size_t need = 0;
+      int q = -1;
+      if (rq.params.precision != s->precision || rq.nsteps < 1 ||
+          !rq.f0_dev || !rq.f_out_dev ||
+          vp_footprint(&rq.params, &need) != VP_OK ||
+          align_up(need) > s->pool_bytes - header_bytes(s->precision)) {
+        res[r].status = VP_EINVAL;
+        res[r].admit_s = res[r].done_s = now_s() - t0;
+        completed += 1;
+        wait_head += 1;
+        continue;
+      }
+      for (int i = 0; i < s->max_active; ++i)
+        if (!s->slot[i].used) {
+          q = i;
+          break;
+        }
+      size_t off = 0;
+      if (q < 0 || !s->alloc.alloc(need, off)) break;
+      vp_ctx *c = nullptr;
+      int r1 = vp_create(&rq.params, s->pool + off, align_up(need), s->stream,
+                         &c);
+      if (r1 == VP_OK) r1 = vp_init_conditions(c, rq.f0_dev, 1);
+      if (r1 != VP_OK) {
+        s->err = c ? c->err : g_create_error;
+        delete c;
+        s->alloc.release(off, need);
+        res[r].status = r1;
+        res[r].admit_s = res[r].done_s = now_s() - t0;
+        completed += 1;
+        wait_head += 1;
+        continue;
+      }
+      Slot &sl = s->slot[q];
+      sl.used = true;
+      sl.c = c;
+      sl.req = r;
+      sl.nsteps = rq.nsteps;
+      sl.done = 0;
+      sl.need_predict = true;
+      sl.off = off;
+      sl.bytes = need;
+      if (s->precision == VP_MIXED)
+        fill_desc<float>(c, rq.f_out_dev, s->runs_host.data() + q * s->rd_size());
+      else
+        fill_desc<double>(c, rq.f_out_dev,
+                          s->runs_host.data() + q * s->rd_size());
+      e = hipMemcpyAsync(reinterpret_cast<char *>(s->runs_dev) + q * s->rd_size(),
+                         s->runs_host.data() + q * s->rd_size(), s->rd_size(),
+                         hipMemcpyHostToDevice, s->stream);
+      if (e != hipSuccess) {
+        rc = srv_fail(s, e, "run table upload");
+        break;
+      }
+      res[r].admit_s = now_s() - t0;
+      active += 1;
+      st.admitted += 1;
+      if (active > st.max_active) st.max_active = active;
+      wait_head += 1;
+    }
+    if (rc) break;
+    if (active == 0 || (int)inflight.size() >= MAX_INFLIGHT ||
+        // every resident run already has all its ticks enqueued
+        [&]() {
+          for (int q = 0; q < s->max_active; ++q)
+            if (s->slot[q].used && s->slot[q].done < s->slot[q].nsteps)
+              return false;
+          return true;
+        }()) {
+      if (!inflight.empty()) {
+        e = hipEventSynchronize(inflight.front().b);
+        if (e != hipSuccess) {
+          rc = srv_fail(s, e, "tick wait");
+          break;
+        }
+        retire(inflight.front(), now_s() - t0);
+        inflight.erase(inflight.begin());
+      } else if (next < n) {
+        const double dt = reqs[next].arrival_s - (now_s() - t0);
+        if (dt > 0)
+          std::this_thread::sleep_for(std::chrono::duration<double>(
+              std::min(dt, 1e-3)));
+      }
+      continue;
+    }
+    // one tick for every resident run
+    Tick tk;
+    tk.ring = ring_pos;
+    ring_pos = (ring_pos + 1) % RING;
+    PhaseTable *tab = s->ring + (size_t)tk.ring * NPH;
+    build_tick(s, tab, tk.finishing);
+    tk.a = get_ev();
+    tk.b = get_ev();
+    if (!tk.a || !tk.b) {
+      rc = srv_fail(s, hipErrorOutOfMemory, "event");
+      break;
+    }
+    (void)hipEventRecord(tk.a, s->stream);
+    e = hipMemcpyAsync(s->tabs_dev, tab, sizeof(PhaseTable) * NPH,
+                       hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+      if (s->use_graph) {
+        e = hipGraphLaunch(s->exec, s->stream);
+      } else {
+        tick_kernels(s);
+        e = hipGetLastError();
+      }
+    }
+    if (e != hipSuccess) {
+      rc = srv_fail(s, e, "tick launch");
+      break;
+    }
+    (void)hipEventRecord(tk.b, s->stream);
+    st.ticks += 1;
+    inflight.push_back(tk);
+  }
+  // drain
+  (void)hipStreamSynchronize(s->stream);
+  while (!inflight.empty()) {
+    retire(inflight.front(), now_s() - t0);
+    inflight.erase(inflight.begin());
+  }
+  for (hipEvent_t ev : evpool) (void)hipEventDestroy(ev);
+  (void)hipEventRecord(ev_in, s->stream);
+  (void)hipStreamWaitEvent(s->caller, ev_in, 0);
+  (void)hipEventDestroy(ev_in);
+  double first = n ? reqs[0].arrival_s : 0.0, last = 0.0;
+  for (int i = 0; i < n; ++i) last = std::max(last, res[i].done_s);
+  st.wall_s = last - first;
+  st.gpu_busy_s = busy;
+  st.completed = completed;
+  if (stats) *stats = st;
+  return rc;
 }
 
 }  // extern "C"

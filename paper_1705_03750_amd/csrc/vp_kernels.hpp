@@ -10,10 +10,11 @@
 //             interior starting at (PV, PX).  F's padding is zero (data
 //             outside the box); C carries mirror ghosts one site deep.
 //   state     element state, SoA [12][E] doubles.
-//   rec       per-element query record, AoS [E][RS] doubles, rebuilt after
-//             every drift: position, A = T^-1, -A/2, H (xv terms doubled),
-//             lattice position Q_m.  One record is 160 B so a wavefront loads
-//             a candidate with a few scalar loads.
+//   rec       per-element query record, AoS [E][16] doubles, rebuilt after
+//             every drift: position, A = T^-1, -A/2, H (xv terms doubled).
+//             One record is 128 B: a wavefront loads a candidate with two
+//             scalar loads, the next one while it evaluates the current.
+//   qm        lattice position Q_m of every element, [E][2] doubles.
 //   cnt, lst  element lists of 8x8-site query blocks: every element whose
 //             validity window can reach a block is listed in that block.
 #pragma once
@@ -25,12 +26,12 @@ namespace vpk {
 
 constexpr int PX = 16;  // x padding of F / C (values)
 constexpr int PV = 2;   // v padding of F / C (rows)
-constexpr int RS = 20;  // doubles per element query record
+constexpr int RS = 16;  // doubles per element query record (128 B)
 constexpr int SPAN_LIMIT = 4096;  // max query blocks one element may enter
 
 enum {
   R_X = 0, R_V, R_AXX, R_AXV, R_AVX, R_AVV, R_NAXX, R_NAXV, R_NAVX, R_NAVV,
-  R_HXXX, R_H2XXV, R_HXVV, R_HVXX, R_H2VXV, R_HVVV, R_QMX, R_QMV, R_RX, R_RV
+  R_HXXX, R_H2XXV, R_HXVV, R_HVXX, R_H2VXV, R_HVVV
 };
 enum {
   S_X = 0, S_V, S_TXX, S_TXV, S_TVX, S_TVV, S_HXXX, S_HXXV, S_HXVV, S_HVXX,
@@ -58,6 +59,15 @@ __device__ __forceinline__ double site_v(const KP &p, int j) {
 // boundaries sit o sites after a multiple of 8; a partial block 0 when o > 0)
 __device__ __forceinline__ int blk(int i, int o, int ob) {
   return ((i - o) >> 3) + ob;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin; give every XCD a
+// contiguous range of the T logical tiles so that its L2 holds the element
+// records and F_ini rows of one band of the grid.
+__device__ __forceinline__ int xcd_tile(int bid, int T) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int base = T >> 3, extra = T & 7;
+  return xcd * base + min(xcd, extra) + idx;
 }
 
 // ------------------------------------------------------------- elements
@@ -155,8 +165,8 @@ __device__ __forceinline__ void elem_kick(const KP &p,
 // the element is non-finite or det T <= 0 (flagged, not registered).
 __device__ __forceinline__ void elem_record(
     const KP &p, const ElemState &s, int e, double *__restrict__ rec,
-    int *__restrict__ cnt, int *__restrict__ lst, int *__restrict__ flags,
-    int reg) {
+    double *__restrict__ qm, int *__restrict__ cnt, int *__restrict__ lst,
+    int *__restrict__ flags, int reg) {
   const double det = fma(s.txx, s.tvv, -(s.txv * s.tvx));
   const bool bad = !(det > 0.0) || !isfinite(det) || !isfinite(s.x) ||
                    !isfinite(s.v);
@@ -181,8 +191,8 @@ __device__ __forceinline__ void elem_record(
   r[R_HVXX] = s.hv0;
   r[R_H2VXV] = 2.0 * s.hv1;
   r[R_HVVV] = s.hv2;
-  r[R_QMX] = site_x(p, p.sx * k + p.sx / 2);
-  r[R_QMV] = site_v(p, p.sv * l + p.sv / 2);
+  qm[2 * (size_t)e] = site_x(p, p.sx * k + p.sx / 2);
+  qm[2 * (size_t)e + 1] = site_v(p, p.sv * l + p.sv / 2);
   // Eulerian reach of the validity window |A dP| < dx_m: |dP_x| <=
   // |Txx| dx_m + |Txv| dv_m, in site units.  The relative margin covers the
   // rounding of l = A dP (it grows with the condition number of T), the
@@ -193,8 +203,6 @@ __device__ __forceinline__ void elem_record(
                          (1.0 + rel) + 0x1p-20;
   const double rvs = (fabs(s.tvx) * p.dxm + fabs(s.tvv) * p.dvm) * p.inv_dv *
                          (1.0 + rel) + 0x1p-20;
-  r[R_RX] = rxs;
-  r[R_RV] = rvs;
   if (bad) {
     atomicOr(flags, FLAG_NUMERIC);
     return;
@@ -213,17 +221,27 @@ __device__ __forceinline__ void elem_record(
     atomicOr(flags, FLAG_WIDE);
     return;
   }
-  for (int bv = b0v; bv <= b1v; ++bv)
-    for (int bx = b0x; bx <= b1x; ++bx) {
-      const int b = bv * p.nbx + bx;
-      const int slot = atomicAdd(&cnt[b], 1);
-      if (slot < p.cap) lst[(size_t)b * p.cap + slot] = e;
+  // slot claims are independent: issue them eight at a time and only then
+  // write the ids (one atomic round trip per eight blocks, not per block)
+  const int wx = b1x - b0x + 1, nblk = wx * (b1v - b0v + 1);
+  for (int q0 = 0; q0 < nblk; q0 += 8) {
+    int bb[8], slot[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int q = q0 + k;
+      bb[k] = (q < nblk) ? (b0v + q / wx) * p.nbx + (b0x + q % wx) : -1;
+      slot[k] = (bb[k] >= 0) ? atomicAdd(&cnt[bb[k]], 1) : p.cap;
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (slot[k] < p.cap) lst[(size_t)bb[k] * p.cap + slot[k]] = e;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_elem(
     KP p, double *__restrict__ st, const double *__restrict__ acc,
-    double *__restrict__ rec, int *__restrict__ cnt_zero, long long nb_zero,
+    double *__restrict__ rec, double *__restrict__ qm,
+    int *__restrict__ cnt_zero, long long nb_zero,
     int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
     int kick, int drift, int predict, int reg) {
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,7 +255,7 @@ __global__ __launch_bounds__(256) void k_elem(
   if (kick) elem_kick(p, acc, s);
   if (predict && drift) elem_drift(p, s);
   if (kick || (predict && drift)) elem_store(st, E, e, s);
-  if (predict) elem_record(p, s, e, rec, cnt_reg, lst, flags, reg);
+  if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
 }
 
 // New isotropic elements (P = Q_m, T = I, H = 0) and cleared block counts.
@@ -281,10 +299,12 @@ __global__ __launch_bounds__(256) void k_fill(T *__restrict__ a, long long n,
 // One candidate of the nearest-element query (sections 1 and 2.3): inverse
 // map of eq. (QofP) with l = A dP, validity |l| < element spacing, squared
 // Lagrangian distance of eq. (distdef) in element-spacing units; the best
-// is the smallest (d^2, id).
-__device__ __forceinline__ void query_candidate(
-    const KP &p, const double *__restrict__ r, int e, double xP, double vP,
-    double &bd, int &best, double &bdqx, double &bdqv) {
+// is the smallest (d^2, id).  r is the candidate's record.
+template <typename R>
+__device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
+                                                double xP, double vP,
+                                                double &bd, int &best,
+                                                double &bdqx, double &bdqv) {
   const double dx = xP - r[R_X], dv = vP - r[R_V];
   const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
   const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
@@ -320,9 +340,22 @@ __device__ __forceinline__ void element_map(const KP &p,
   dqv = fma(r[R_NAVX], ux, fma(r[R_NAVV], uv, lv));
 }
 
+struct Rec {
+  double v[RS];
+  __device__ __forceinline__ double operator[](int k) const { return v[k]; }
+};
+
+__device__ __forceinline__ void load_rec(const double *__restrict__ rec,
+                                         int e, Rec &r) {
+  const double *q = rec + (size_t)e * RS;
+#pragma unroll
+  for (int k = 0; k < RS; ++k) r.v[k] = q[k];
+}
+
 // Nearest element of (xP, vP) from the wave's block list (uniform over the
-// wavefront: candidate records come through scalar loads), or from all
-// elements when the list overflowed or an element was too wide to list.
+// wavefront: a candidate's record is one 128-B scalar load, the next list
+// entry is requested a candidate ahead), or from all elements when the list
+// overflowed or an element was too wide to list.
 __device__ __forceinline__ int query_block(
     const KP &p, const double *__restrict__ rec, const int *__restrict__ lst,
     int b, int n, bool scan_all, double xP, double vP, double &dqx,
@@ -332,14 +365,42 @@ __device__ __forceinline__ int query_block(
   dqx = 0.0;
   dqv = 0.0;
   if (!scan_all) {
-    const int *L = lst + (size_t)b * p.cap;
-    for (int c = 0; c < n; ++c) {
-      const int e = __builtin_amdgcn_readfirstlane(L[c]);
-      query_candidate(p, rec + (size_t)e * RS, e, xP, vP, bd, best, dqx, dqv);
+    if (n <= 0) return best;
+    // list ids four at a time (one scalar load; rows are 16-int aligned and
+    // cap is a multiple of 16, so the read stays inside the row)
+    const int4 *L4 = reinterpret_cast<const int4 *>(lst + (size_t)b * p.cap);
+    int4 ids = L4[0];
+    for (int c0 = 0; c0 < n; c0 += 4) {
+      // the next four ids travel with the first record of this chunk
+      const int4 nxt = (c0 + 4 < n) ? L4[(c0 >> 2) + 1] : ids;
+      const int id4[4] = {ids.x, ids.y, ids.z, ids.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (c0 + k >= n) break;
+        const int e = id4[k];
+        Rec r;
+        load_rec(rec, e, r);
+        // All 16 values are wanted before the validity branch: one batch of
+        // scalar loads (one memory round trip) instead of a second batch
+        // inside the branch.  The empty statement emits no instruction.
+        __asm__ volatile("" ::"s"(r.v[0]), "s"(r.v[1]), "s"(r.v[2]),
+                         "s"(r.v[3]), "s"(r.v[4]), "s"(r.v[5]), "s"(r.v[6]),
+                         "s"(r.v[7]), "s"(r.v[8]), "s"(r.v[9]), "s"(r.v[10]),
+                         "s"(r.v[11]), "s"(r.v[12]), "s"(r.v[13]),
+                         "s"(r.v[14]), "s"(r.v[15]));
+        if (k == 0)
+          __asm__ volatile("" ::"s"(nxt.x), "s"(nxt.y), "s"(nxt.z),
+                           "s"(nxt.w));
+        query_candidate(p, r, e, xP, vP, bd, best, dqx, dqv);
+      }
+      ids = nxt;
     }
   } else {
-    for (int e = 0; e < p.E; ++e)
-      query_candidate(p, rec + (size_t)e * RS, e, xP, vP, bd, best, dqx, dqv);
+    for (int e = 0; e < p.E; ++e) {
+      Rec r;
+      load_rec(rec, e, r);
+      query_candidate(p, r, e, xP, vP, bd, best, dqx, dqv);
+    }
   }
   return best;
 }
@@ -447,39 +508,48 @@ __device__ __forceinline__ double Ml_at(const double *Ml, int nx, double Mtot,
 
 // The field computation of one workgroup (any size): `in` holds S (column
 // sums) or rho; ATOMIC_IN reads it with device-coherent loads (used when
-// other workgroups of the same kernel wrote it).
+// other workgroups of the same kernel wrote it).  The 256-site chunks of
+// the cumulative sum go through LDS `stage` (stage_n doubles, a multiple of
+// 256) in rounds: all threads fill it, one thread per chunk runs the
+// sequential sum on it, all threads write it back.
 template <bool ATOMIC_IN>
 __device__ __forceinline__ void field_wg(
     const KP &p, const double *__restrict__ in, int in_is_rho,
-    double *__restrict__ Mw, double *__restrict__ Ml, double *__restrict__ acc,
+    double *__restrict__ Ml, double *__restrict__ acc,
     double *__restrict__ rho_out, double *__restrict__ a_out,
     double *__restrict__ da_out, double *__restrict__ d2a_out, double *tot,
-    double *car) {
+    double *car, double *stage, int stage_n) {
   const int nx = p.nx, tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < nx; i += nt) {
-    double x;
-    if (ATOMIC_IN)
-      x = __longlong_as_double((long long)__hip_atomic_load(
-          reinterpret_cast<const unsigned long long *>(in) + i,
-          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    else
-      x = in[i];
-    const double rho = in_is_rho ? x : p.dv * x;
-    if (rho_out) rho_out[i] = rho;
-    Mw[i] = p.dx * rho;
-  }
-  __syncthreads();
-  const int nch = (nx + 255) / 256;
-  for (int c = tid; c < nch; c += nt) {
-    const int c1 = min(nx, 256 * c + 256);
-    double s = 0.0;
-    for (int i = 256 * c; i < c1; ++i) {
-      s += Mw[i];
-      Ml[i] = s;
+  for (int r0 = 0; r0 < nx; r0 += stage_n) {
+    const int rn = min(stage_n, nx - r0);
+    for (int q = tid; q < rn; q += nt) {
+      const int i = r0 + q;
+      double x;
+      if (ATOMIC_IN)
+        x = __longlong_as_double((long long)__hip_atomic_load(
+            reinterpret_cast<const unsigned long long *>(in) + i,
+            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      else
+        x = in[i];
+      const double rho = in_is_rho ? x : p.dv * x;
+      if (rho_out) rho_out[i] = rho;
+      stage[q] = p.dx * rho;
     }
-    tot[c] = s;
+    __syncthreads();
+    for (int c = tid; c * 256 < rn; c += nt) {
+      const int q1 = min(rn, c * 256 + 256);
+      double s = 0.0;
+      for (int q = c * 256; q < q1; ++q) {
+        s += stage[q];
+        stage[q] = s;
+      }
+      tot[(r0 >> 8) + c] = s;
+    }
+    __syncthreads();
+    for (int q = tid; q < rn; q += nt) Ml[r0 + q] = stage[q];
+    __syncthreads();
   }
-  __syncthreads();
+  const int nch = (nx + 255) / 256;
   if (tid == 0) {
     double carry = 0.0;
     for (int c = 0; c < nch; ++c) {
@@ -517,14 +587,15 @@ __device__ __forceinline__ void field_wg(
 constexpr int FIELD_CHUNKS = 1024;  // up to 262144 columns
 
 __global__ __launch_bounds__(1024) void k_field(
-    KP p, const double *__restrict__ in, int in_is_rho, double *__restrict__ Mw,
+    KP p, const double *__restrict__ in, int in_is_rho,
     double *__restrict__ Ml, double *__restrict__ acc,
     double *__restrict__ rho_out, double *__restrict__ a_out,
     double *__restrict__ da_out, double *__restrict__ d2a_out) {
   __shared__ double tot[FIELD_CHUNKS];
   __shared__ double car[FIELD_CHUNKS];
-  field_wg<false>(p, in, in_is_rho, Mw, Ml, acc, rho_out, a_out, da_out,
-                  d2a_out, tot, car);
+  __shared__ double stage[4096];
+  field_wg<false>(p, in, in_is_rho, Ml, acc, rho_out, a_out, da_out, d2a_out,
+                  tot, car, stage, 4096);
 }
 
 // ------------------------------------------------------- reconstruction
@@ -537,21 +608,21 @@ __global__ __launch_bounds__(1024) void k_field(
 // those computes the force for the whole grid (field_wg), so one launch
 // covers density projection and Poisson solve.
 template <typename FT, int MODE>
-__global__ __launch_bounds__(512) void k_recon(
-    KP p, const double *__restrict__ rec, const int *__restrict__ cnt,
+__device__ __forceinline__ void recon_tile(
+    KP p, const double *__restrict__ rec, const double *__restrict__ qm,
+    const int *__restrict__ cnt,
     const int *__restrict__ lst, const int *__restrict__ flags,
     const FT *__restrict__ F, double *__restrict__ part,
     int *__restrict__ colcnt, double *__restrict__ S, FT *__restrict__ fout,
     int *__restrict__ aout, double *__restrict__ dpart,
     unsigned long long *__restrict__ ovf, int *__restrict__ donecnt,
     double *__restrict__ Mw, double *__restrict__ Ml, double *__restrict__ acc,
-    double *__restrict__ rho_out) {
+    double *__restrict__ rho_out, const int bx, const int gy) {
   __shared__ double sf[512];
   __shared__ double sk[512];
   __shared__ int s_last;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int bx = blockIdx.x, gy = blockIdx.y;
   const int bv = 8 * (gy - p.obv) + p.obv + w;
   const int i = p.ox + 8 * (bx - p.obx) + (lane & 7);
   const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
@@ -568,8 +639,8 @@ __global__ __launch_bounds__(512) void k_recon(
     double dqx, dqv;
     best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv);
     if (live && best >= 0) {
-      const double *r = rec + (size_t)best * RS;
-      const double Qx = r[R_QMX] + dqx, Qv = r[R_QMV] + dqv;
+      const double Qx = qm[2 * (size_t)best] + dqx;
+      const double Qv = qm[2 * (size_t)best + 1] + dqv;
       const double sx = (Qx - p.x_min) * p.inv_dx - 0.5;
       const double sv = (Qv - p.v_min) * p.inv_dv - 0.5;
       const FT *F0 = F + (long)PV * p.pitch + PX;
@@ -602,7 +673,7 @@ __global__ __launch_bounds__(512) void k_recon(
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const size_t wg = (size_t)gy * gridDim.x + bx;
+      const size_t wg = (size_t)gy * p.nbx + bx;
       dpart[2 * wg] = sk[0];
       dpart[2 * wg + 1] = se[0];
     }
@@ -648,10 +719,28 @@ __global__ __launch_bounds__(512) void k_recon(
   }
   __syncthreads();
   if (!s_last) return;
-  field_wg<true>(p, S, 0, Mw, Ml, acc, rho_out, nullptr, nullptr, nullptr, sf,
-                 sk);
+  __shared__ double stage[1024];
+  field_wg<true>(p, S, 0, Ml, acc, rho_out, nullptr, nullptr, nullptr, sf, sk,
+                 stage, 1024);
   if (threadIdx.x == 0)
     __hip_atomic_store(donecnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename FT, int MODE>
+__global__ __launch_bounds__(512) void k_recon(
+    KP p, const double *__restrict__ rec, const double *__restrict__ qm,
+    const int *__restrict__ cnt,
+    const int *__restrict__ lst, const int *__restrict__ flags,
+    const FT *__restrict__ F, double *__restrict__ part,
+    int *__restrict__ colcnt, double *__restrict__ S, FT *__restrict__ fout,
+    int *__restrict__ aout, double *__restrict__ dpart,
+    unsigned long long *__restrict__ ovf, int *__restrict__ donecnt,
+    double *__restrict__ Mw, double *__restrict__ Ml, double *__restrict__ acc,
+    double *__restrict__ rho_out) {
+  const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
+  recon_tile<FT, MODE>(p, rec, qm, cnt, lst, flags, F, part, colcnt, S, fout,
+                       aout, dpart, ovf, donecnt, Mw, Ml, acc, rho_out,
+                       t % p.nbx, t / p.nbx);
 }
 
 // Resampling value at every site (section 2.3.2): nearest element, the
@@ -660,14 +749,14 @@ __global__ __launch_bounds__(512) void k_recon(
 // F_ini at Q_r; the outermost ring is zero.  Writes F (padded interior)
 // when TO_F == 0, else f_out.
 template <typename FT, int TO_F>
-__global__ __launch_bounds__(512) void k_remap_eval(
-    KP p, const double *__restrict__ rec, const int *__restrict__ cnt,
+__device__ __forceinline__ void remap_tile(
+    KP p, const double *__restrict__ rec, const double *__restrict__ qm,
+    const int *__restrict__ cnt,
     const int *__restrict__ lst, const int *__restrict__ flags,
     const FT *__restrict__ C, FT *__restrict__ Fout,
-    unsigned long long *__restrict__ ovf) {
+    unsigned long long *__restrict__ ovf, const int bx, const int gy) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int bx = blockIdx.x, gy = blockIdx.y;
   const int bv = 8 * (gy - p.obv) + p.obv + w;
   if (bv < 0 || bv >= p.nbv) return;
   const int i = p.ox + 8 * (bx - p.obx) + (lane & 7);
@@ -695,10 +784,10 @@ __global__ __launch_bounds__(512) void k_remap_eval(
         if (three && dk != 0 && dl != 0) continue;
         const int k = k0 + dk, l = l0 + dl;
         if (k < 0 || k >= p.mx || l < 0 || l >= p.mv) continue;
-        const double *r = rec + (size_t)(l * p.mx + k) * RS;
+        const size_t m = (size_t)(l * p.mx + k);
         double ex, ev;
-        element_map(p, r, xP, vP, ex, ev);
-        const double qx = r[R_QMX] + ex, qv = r[R_QMV] + ev;
+        element_map(p, rec + m * RS, xP, vP, ex, ev);
+        const double qx = qm[2 * m] + ex, qv = qm[2 * m + 1] + ev;
         const double ax = ex * p.rx, av = ev * p.rv;
         const double d = sqrt(fma(ax, ax, av * av));
         const double wt = W_kernel(2.0 * d);
@@ -712,9 +801,8 @@ __global__ __launch_bounds__(512) void k_remap_eval(
       Qx = sqx / sw;
       Qv = sqv / sw;
     } else {
-      const double *r = rec + (size_t)best * RS;
-      Qx = r[R_QMX] + dqx;
-      Qv = r[R_QMV] + dqv;
+      Qx = qm[2 * (size_t)best] + dqx;
+      Qv = qm[2 * (size_t)best + 1] + dqv;
     }
     const double sx = (Qx - p.x_min) * p.inv_dx - 0.5;
     const double sv = (Qv - p.v_min) * p.inv_dv - 0.5;
@@ -725,6 +813,18 @@ __global__ __launch_bounds__(512) void k_remap_eval(
     Fout[(long)(j + PV) * p.pitch + (i + PX)] = val;
   else
     Fout[(size_t)j * p.nx + i] = val;
+}
+
+template <typename FT, int TO_F>
+__global__ __launch_bounds__(512) void k_remap_eval(
+    KP p, const double *__restrict__ rec, const double *__restrict__ qm,
+    const int *__restrict__ cnt,
+    const int *__restrict__ lst, const int *__restrict__ flags,
+    const FT *__restrict__ C, FT *__restrict__ Fout,
+    unsigned long long *__restrict__ ovf) {
+  const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
+  remap_tile<FT, TO_F>(p, rec, qm, cnt, lst, flags, C, Fout, ovf, t % p.nbx,
+                       t / p.nbx);
 }
 
 // Diagnostics (section 3.2): sums of the per-workgroup partials, potential
@@ -797,110 +897,152 @@ __global__ __launch_bounds__(1024) void k_diag(
 
 // Tridiagonal (1, 4, 1) solve with end rows (4, 2) / (2, 4) along x for
 // every row (Thomas elimination; the row-independent pivots cp and 1/den are
-// precomputed).  One thread per row; the row is staged through LDS in
-// 64-value chunks so that global reads and writes stay coalesced.
+// precomputed).  One thread per row; the recurrence is strictly sequential
+// along the row, so each thread reads its row 16 values at a time (one
+// memory round trip per 16 sites) and runs the recurrence on registers.
+constexpr int FIT_CH = 16;
+
+template <typename FT>
+__device__ __forceinline__ void fit_x_rows(const KP &p, const FT *__restrict__ F,
+                                          FT *__restrict__ T,
+                                          const FT *__restrict__ cpx,
+                                          const FT *__restrict__ rix,
+                                          const int chunk) {
+  const int j = chunk * 64 + threadIdx.x;
+  const int nx = p.nx;
+  if (j >= p.nv) return;
+  const FT *Fr = F + (long)(j + PV) * p.pitch + PX;
+  FT *Tr = T + (size_t)j * nx;
+  FT dp = (FT)0;
+  // forward sweep
+  for (int i0 = 0; i0 < nx; i0 += FIT_CH) {
+    FT v[FIT_CH];
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k) v[k] = (i0 + k < nx) ? Fr[i0 + k] : (FT)0;
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k) {
+      const int i = i0 + k;
+      if (i >= nx) break;
+      if (i == 0) {
+        dp = ((FT)6 * v[k]) * rix[0];
+      } else {
+        const FT sub = (i == nx - 1) ? (FT)2 : (FT)1;
+        dp = ((FT)6 * v[k] - sub * dp) * rix[i];
+      }
+      v[k] = dp;
+    }
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k)
+      if (i0 + k < nx) Tr[i0 + k] = v[k];
+  }
+  // back substitution, chunks in reverse
+  FT out = (FT)0;
+  const int last0 = ((nx - 1) / FIT_CH) * FIT_CH;
+  for (int i0 = last0; i0 >= 0; i0 -= FIT_CH) {
+    FT v[FIT_CH];
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k) v[k] = (i0 + k < nx) ? Tr[i0 + k] : (FT)0;
+#pragma unroll
+    for (int k = FIT_CH - 1; k >= 0; --k) {
+      const int i = i0 + k;
+      if (i >= nx) continue;
+      out = (i == nx - 1) ? v[k] : v[k] - cpx[i] * out;
+      v[k] = out;
+    }
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k)
+      if (i0 + k < nx) Tr[i0 + k] = v[k];
+  }
+}
+
 template <typename FT>
 __global__ __launch_bounds__(64) void k_fit_x(KP p, const FT *__restrict__ F,
                                               FT *__restrict__ T,
                                               const FT *__restrict__ cpx,
                                               const FT *__restrict__ rix) {
-  __shared__ FT tile[64][65];
-  const int lane = threadIdx.x;
-  const int j0 = blockIdx.x * 64;
-  const int nx = p.nx, nv = p.nv;
-  const long pt = p.pitch;
-  const FT *F0 = F + (long)PV * pt + PX;
-  FT dp = (FT)0;
-  // forward sweep
-  for (int c0 = 0; c0 < nx; c0 += 64) {
-    for (int r = 0; r < 64; ++r) {
-      const int j = j0 + r, i = c0 + lane;
-      tile[r][lane] = (j < nv && i < nx) ? F0[(long)j * pt + i] : (FT)0;
-    }
-    __syncthreads();
-    const int cend = min(64, nx - c0);
-    for (int c = 0; c < cend; ++c) {
-      const int i = c0 + c;
-      const FT fv = tile[lane][c];
-      if (i == 0) {
-        dp = ((FT)6 * fv) * rix[0];
-      } else {
-        const FT sub = (i == nx - 1) ? (FT)2 : (FT)1;
-        dp = ((FT)6 * fv - sub * dp) * rix[i];
-      }
-      tile[lane][c] = dp;
-    }
-    __syncthreads();
-    for (int r = 0; r < 64; ++r) {
-      const int j = j0 + r, i = c0 + lane;
-      if (j < nv && i < nx) T[(size_t)j * nx + i] = tile[r][lane];
-    }
-    __syncthreads();
-  }
-  // back substitution, chunks in reverse
-  FT out = (FT)0;
-  const int lastc = ((nx - 1) / 64) * 64;
-  for (int c0 = lastc; c0 >= 0; c0 -= 64) {
-    for (int r = 0; r < 64; ++r) {
-      const int j = j0 + r, i = c0 + lane;
-      tile[r][lane] = (j < nv && i < nx) ? T[(size_t)j * nx + i] : (FT)0;
-    }
-    __syncthreads();
-    const int cend = min(64, nx - c0);
-    for (int c = cend - 1; c >= 0; --c) {
-      const int i = c0 + c;
-      const FT d = tile[lane][c];
-      out = (i == nx - 1) ? d : d - cpx[i] * out;
-      tile[lane][c] = out;
-    }
-    __syncthreads();
-    for (int r = 0; r < 64; ++r) {
-      const int j = j0 + r, i = c0 + lane;
-      if (j < nv && i < nx) T[(size_t)j * nx + i] = tile[r][lane];
-    }
-    __syncthreads();
-  }
+  fit_x_rows<FT>(p, F, T, cpx, rix, blockIdx.x);
 }
 
+
 // The same solve along v for every column (one thread per column: rows are
-// read and written coalesced), written into C with mirror ghost rows.
+// read and written coalesced, 16 rows per memory round trip), written into
+// C with mirror ghost rows.
 template <typename FT>
-__global__ __launch_bounds__(64) void k_fit_v(KP p, const FT *__restrict__ T,
-                                              FT *__restrict__ C,
-                                              const FT *__restrict__ cpv,
-                                              const FT *__restrict__ riv) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
+__device__ __forceinline__ void fit_v_cols(const KP &p, const FT *__restrict__ T,
+                                          FT *__restrict__ C,
+                                          const FT *__restrict__ cpv,
+                                          const FT *__restrict__ riv,
+                                          const int chunk) {
+  const int i = chunk * 64 + threadIdx.x;
   const int nx = p.nx, nv = p.nv;
   if (i >= nx) return;
   const long pt = p.pitch;
   FT *C0 = C + (long)PV * pt + PX + i;
-  FT dp = ((FT)6 * T[i]) * riv[0];
-  C0[0] = dp;
-  for (int j = 1; j < nv; ++j) {
-    const FT sub = (j == nv - 1) ? (FT)2 : (FT)1;
-    dp = ((FT)6 * T[(size_t)j * nx + i] - sub * dp) * riv[j];
-    C0[(long)j * pt] = dp;
+  FT dp = (FT)0;
+  for (int j0 = 0; j0 < nv; j0 += FIT_CH) {
+    FT v[FIT_CH];
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k)
+      v[k] = (j0 + k < nv) ? T[(size_t)(j0 + k) * nx + i] : (FT)0;
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k) {
+      const int j = j0 + k;
+      if (j >= nv) break;
+      if (j == 0) {
+        dp = ((FT)6 * v[k]) * riv[0];
+      } else {
+        const FT sub = (j == nv - 1) ? (FT)2 : (FT)1;
+        dp = ((FT)6 * v[k] - sub * dp) * riv[j];
+      }
+      C0[(long)j * pt] = dp;
+    }
   }
-  FT out = dp;
-  for (int j = nv - 2; j >= 0; --j) {
-    out = C0[(long)j * pt] - cpv[j] * out;
-    C0[(long)j * pt] = out;
+  FT out = (FT)0;
+  const int last0 = ((nv - 1) / FIT_CH) * FIT_CH;
+  for (int j0 = last0; j0 >= 0; j0 -= FIT_CH) {
+    FT v[FIT_CH];
+#pragma unroll
+    for (int k = 0; k < FIT_CH; ++k)
+      v[k] = (j0 + k < nv) ? C0[(long)(j0 + k) * pt] : (FT)0;
+#pragma unroll
+    for (int k = FIT_CH - 1; k >= 0; --k) {
+      const int j = j0 + k;
+      if (j >= nv) continue;
+      out = (j == nv - 1) ? v[k] : v[k] - cpv[j] * out;
+      C0[(long)j * pt] = out;
+    }
   }
   C0[-pt] = C0[pt];
   C0[(long)nv * pt] = C0[(long)(nv - 2) * pt];
 }
 
+template <typename FT>
+__global__ __launch_bounds__(64) void k_fit_v(KP p, const FT *__restrict__ T,
+                                              FT *__restrict__ C,
+                                              const FT *__restrict__ cpv,
+                                              const FT *__restrict__ riv) {
+  fit_v_cols<FT>(p, T, C, cpv, riv, blockIdx.x);
+}
+
+
 // Mirror ghost columns c(-1, j) = c(1, j), c(nx, j) = c(nx - 2, j) for
 // j in [-1, nv] (corners follow from the ghost rows).
 template <typename FT>
-__global__ __launch_bounds__(256) void k_ghost_x(KP p, FT *__restrict__ C) {
-  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x) - 1;
+__device__ __forceinline__ void ghost_x_rows(const KP &p, FT *__restrict__ C,
+                                            const int chunk) {
+  const int j = chunk * 256 + (int)threadIdx.x - 1;
   if (j > p.nv) return;
   const long pt = p.pitch;
   FT *row = C + (long)(j + PV) * pt + PX;
   row[-1] = row[1];
   row[p.nx] = row[p.nx - 2];
 }
+
+template <typename FT>
+__global__ __launch_bounds__(256) void k_ghost_x(KP p, FT *__restrict__ C) {
+  ghost_x_rows<FT>(p, C, blockIdx.x);
+}
+
 
 // Rows [j0, j0 + nrows) of f0 (double, src holds those rows) -> F (padded
 // interior), the outermost ring zeroed.
