@@ -28,7 +28,8 @@ struct PhaseTable {
 // Phases of one tick, in launch order.
 enum {
   PH_PRED = 0,    // predictor drift + records + block lists (first step)
-  PH_RECON,       // reconstruction + column sums + force
+  PH_RECON,       // reconstruction + row-group column partials
+  PH_FIELD,       // column sums, cumulative mass, force
   PH_KICK,        // kick + corrector (+ next predictor when continuing)
   PH_RM_PRED,     // remap: records + lists of the post-corrector elements
   PH_RM_EVAL,     // remap evaluation into F_ini
@@ -52,8 +53,8 @@ template <typename FT>
 struct RunDesc {
   KP k;
   long long nb;
-  double *st, *rec, *qm, *part, *S, *Mw, *Ml, *acc, *dpart;
-  int *cnt, *lst, *flags, *colcnt;
+  double *st, *rec, *qm, *part, *Mc, *ctot, *Ml, *acc, *dpart;
+  int *cnt, *lst, *flags, *fcnt;
   unsigned long long *ovf;
   FT *F, *C, *T;
   const FT *tab;
@@ -129,9 +130,32 @@ __global__ __launch_bounds__(512) void kb_recon(
     const int local = item - pi.begin;
     const int bx = local % R.k.nbx, gy = local / R.k.nbx;
     recon_tile<FT, MODE>(R.k, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
-                         R.flags, R.F, R.part, R.colcnt, R.S, R.fout, nullptr,
-                         R.dpart, R.ovf, R.colcnt + R.k.nbx, R.Mw, R.Ml, R.acc,
-                         nullptr, bx, gy);
+                         R.flags, R.F, R.part, R.fout, nullptr, R.dpart, R.ovf,
+                         bx, gy);
+  }
+}
+
+// Field chunks (256 columns per item) from the row-group partials.
+template <typename FT>
+__global__ __launch_bounds__(FIELD_WG) void kb_field(
+    const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  __shared__ FieldLds L;
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    __syncthreads();
+    const int q = find_run(tab, item);
+    const PhaseItem pi = tab->it[q];
+    const RunDesc<FT> &R = runs[pi.slot];
+    FieldArgs A{};
+    A.in = R.part;
+    A.ngy = R.k.ngy;
+    A.in_is_rho = 0;
+    A.Mc = R.Mc;
+    A.ctot = R.ctot;
+    A.fcnt = R.fcnt;
+    A.Ml = R.Ml;
+    A.acc = R.acc;
+    field_chunk(R.k, A, item - pi.begin, L);
   }
 }
 
@@ -151,22 +175,23 @@ __global__ __launch_bounds__(512) void kb_remap(
 }
 
 template <typename FT>
-__global__ __launch_bounds__(64) void kb_fit_x(
+__global__ __launch_bounds__(FIT_THREADS) void kb_fit_x(
     const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  __shared__ FitLds<FT> S;
   const int total = tab->total;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    __syncthreads();
     const int q = find_run(tab, item);
     const PhaseItem pi = tab->it[q];
     const RunDesc<FT> &R = runs[pi.slot];
     const KP &p = R.k;
-    fit_x_rows<FT>(p, R.F, R.T, R.tab, R.tab + p.nx, item - pi.begin);
+    fit_x_rows<FT>(p, R.F, R.T, R.tab, R.tab + p.nx, item - pi.begin, S);
   }
 }
 
 template <typename FT>
-__global__ __launch_bounds__(64) void kb_fit_v(
+__global__ __launch_bounds__(FIT_THREADS) void kb_fit_v(
     const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  __shared__ FitLds<FT> S;
   const int total = tab->total;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int q = find_run(tab, item);
@@ -174,7 +199,7 @@ __global__ __launch_bounds__(64) void kb_fit_v(
     const RunDesc<FT> &R = runs[pi.slot];
     const KP &p = R.k;
     fit_v_cols<FT>(p, R.T, R.C, R.tab + 2 * p.nx, R.tab + 2 * p.nx + p.nv,
-                   item - pi.begin);
+                   item - pi.begin, S);
   }
 }
 

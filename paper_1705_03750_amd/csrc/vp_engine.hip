@@ -3,7 +3,8 @@
 //
 // Every step runs: k_elem_predict (predictor drift, A = T^-1, query-block
 // lists) -> k_recon (nearest element, inverse map, six-point interpolation,
-// column sums) -> k_field (cumulative mass, force and derivatives) ->
+// row-group column partials) -> k_field (column sums, cumulative mass,
+// force and derivatives) ->
 // k_elem_kick (TSC, kick, corrector drift); every n_s steps the resampling
 // k_elem_predict -> k_remap_eval -> k_fit_x -> k_fit_v -> k_ghost_x ->
 // k_elem_reset.  Nothing is allocated: all buffers live in the caller's
@@ -33,7 +34,7 @@ namespace {
 thread_local std::string g_create_error;
 
 struct Layout {
-  size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, colcnt, S, Mw, Ml, acc,
+  size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, fcnt, Mc, ctot, Ml, acc,
       dpart, dout, tab, total;
   size_t fbytes;  // bytes per f value
   long long nb;
@@ -128,9 +129,9 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.flags = take(64);
   L.ovf = take(64);
   L.part = take((size_t)k.ngy * k.nx * 8);
-  L.colcnt = take((size_t)(k.nbx + 64) * 4);  // + the done-block counter
-  L.S = take((size_t)k.nx * 8);
-  L.Mw = take((size_t)k.nx * 8);
+  L.fcnt = take(64);
+  L.Mc = take((size_t)k.nx * 8);
+  L.ctot = take((size_t)FIELD_CHUNKS * 8);
   L.Ml = take((size_t)k.nx * 8);
   L.acc = take((size_t)3 * (k.nx + 8) * 8);
   L.dpart = take((size_t)2 * k.nbx * k.ngy * 8);
@@ -254,32 +255,45 @@ int launch_recon(vp_ctx *c, void *fout, int *aout, double *rho_out) {
                      c->at<double>(c->L.qm), c->counts(c->cur),
                      c->at<int>(c->L.lst), c->at<int>(c->L.flags),
                      c->at<FT>(c->L.F),
-                     c->at<double>(c->L.part), c->at<int>(c->L.colcnt),
-                     c->at<double>(c->L.S), reinterpret_cast<FT *>(fout), aout,
-                     c->at<double>(c->L.dpart),
-                     c->at<unsigned long long>(c->L.ovf),
-                     c->at<int>(c->L.colcnt) + k.nbx, c->at<double>(c->L.Mw),
-                     c->at<double>(c->L.Ml), c->at<double>(c->L.acc), rho_out);
+                     c->at<double>(c->L.part), reinterpret_cast<FT *>(fout),
+                     aout, c->at<double>(c->L.dpart),
+                     c->at<unsigned long long>(c->L.ovf));
   VP_LAUNCH_CHECK(c, "k_recon");
   return VP_OK;
 }
 
-// The reconstruction in one of its modes; the density modes also compute
-// the force (a, a', a'') and optionally write rho.
-template <int MODE>
-int recon(vp_ctx *c, void *fout, int *aout, double *rho_out = nullptr) {
-  return c->mixed() ? launch_recon<float, MODE>(c, fout, aout, rho_out)
-                    : launch_recon<double, MODE>(c, fout, aout, rho_out);
-}
-
-int launch_field(vp_ctx *c, const double *in, int in_is_rho, double *rho_out,
+int launch_field(vp_ctx *c, const double *in, int from_part, double *rho_out,
                  double *a_out, double *da_out, double *d2a_out) {
   ProfScope ps(c, PK_FIELD);
-  hipLaunchKernelGGL(k_field, dim3(1), dim3(1024), 0, c->stream, c->k, in,
-                     in_is_rho, c->at<double>(c->L.Ml),
-                     c->at<double>(c->L.acc), rho_out, a_out, da_out, d2a_out);
+  FieldArgs A{};
+  A.in = in;
+  A.ngy = from_part ? c->k.ngy : 0;
+  A.in_is_rho = from_part ? 0 : 1;
+  A.Mc = c->at<double>(c->L.Mc);
+  A.ctot = c->at<double>(c->L.ctot);
+  A.fcnt = c->at<int>(c->L.fcnt);
+  A.Ml = c->at<double>(c->L.Ml);
+  A.acc = c->at<double>(c->L.acc);
+  A.rho_out = rho_out;
+  A.a_out = a_out;
+  A.da_out = da_out;
+  A.d2a_out = d2a_out;
+  const int nch = (c->k.nx + FIELD_WG - 1) / FIELD_WG;
+  hipLaunchKernelGGL(k_field, dim3(nch), dim3(FIELD_WG), 0, c->stream, c->k,
+                     A);
   VP_LAUNCH_CHECK(c, "k_field");
   return VP_OK;
+}
+
+// The reconstruction in one of its modes; the density modes are followed
+// by the field pass (a, a', a'', optionally rho).
+template <int MODE>
+int recon(vp_ctx *c, void *fout, int *aout, double *rho_out = nullptr) {
+  const int rc = c->mixed() ? launch_recon<float, MODE>(c, fout, aout, rho_out)
+                            : launch_recon<double, MODE>(c, fout, aout, rho_out);
+  if (rc || (MODE != MODE_DENSITY && MODE != MODE_DIAG)) return rc;
+  return launch_field(c, c->at<double>(c->L.part), 1, rho_out, nullptr,
+                      nullptr, nullptr);
 }
 
 int launch_reset(vp_ctx *c) {
@@ -300,11 +314,13 @@ int fit_spline_t(vp_ctx *c) {
   FT *tab = c->at<FT>(c->L.tab);
   FT *cpx = tab, *rix = tab + k.nx, *cpv = tab + 2 * k.nx,
      *riv = tab + 2 * k.nx + k.nv;
-  hipLaunchKernelGGL((k_fit_x<FT>), dim3(grid_for(k.nv, 64)), dim3(64), 0,
+  hipLaunchKernelGGL((k_fit_x<FT>), dim3(grid_for(k.nv, FIT_LINES)),
+                     dim3(FIT_THREADS), 0,
                      c->stream, k, c->at<FT>(c->L.F), c->at<FT>(c->L.T), cpx,
                      rix);
   VP_LAUNCH_CHECK(c, "k_fit_x");
-  hipLaunchKernelGGL((k_fit_v<FT>), dim3(grid_for(k.nx, 64)), dim3(64), 0,
+  hipLaunchKernelGGL((k_fit_v<FT>), dim3(grid_for(k.nx, FIT_LINES)),
+                     dim3(FIT_THREADS), 0,
                      c->stream, k, c->at<FT>(c->L.T), c->at<FT>(c->L.C), cpv,
                      riv);
   VP_LAUNCH_CHECK(c, "k_fit_v");
@@ -584,7 +600,7 @@ int vp_density(vp_ctx *c, double *rho_out_dev) {
 int vp_poisson(vp_ctx *c, const double *rho, double *a, double *da,
                double *d2a) {
   if (!c || !rho || !a || !da || !d2a) return VP_EINVAL;
-  return launch_field(c, rho, 1, nullptr, a, da, d2a);
+  return launch_field(c, rho, 0, nullptr, a, da, d2a);
 }
 
 int vp_diagnostics(vp_ctx *c, vp_diag *out) {
@@ -767,6 +783,7 @@ constexpr int MAX_INFLIGHT = 3;  // ticks enqueued ahead of the device
 constexpr int GRID_TILE = 2048;  // fixed grids of the batched kernels
 constexpr int GRID_ELEM = 2048;
 constexpr int GRID_FIT = 1024;
+constexpr int GRID_FIELD = 256;
 
 size_t header_bytes(int precision) {
   const size_t rd = precision == VP_MIXED ? sizeof(RunDesc<float>)
@@ -815,16 +832,18 @@ void launch_tick_kernels(vp_server *s) {
                      t + PH_PRED);
   hipLaunchKernelGGL((kb_recon<FT, MODE_DENSITY>), dim3(GRID_TILE), dim3(512),
                      0, st, runs, t + PH_RECON);
+  hipLaunchKernelGGL(kb_field<FT>, dim3(GRID_FIELD), dim3(FIELD_WG), 0, st,
+                     runs, t + PH_FIELD);
   hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
                      t + PH_KICK);
   hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
                      t + PH_RM_PRED);
   hipLaunchKernelGGL(kb_remap<FT>, dim3(GRID_TILE), dim3(512), 0, st, runs,
                      t + PH_RM_EVAL);
-  hipLaunchKernelGGL(kb_fit_x<FT>, dim3(GRID_FIT), dim3(64), 0, st, runs,
-                     t + PH_FIT_X);
-  hipLaunchKernelGGL(kb_fit_v<FT>, dim3(GRID_FIT), dim3(64), 0, st, runs,
-                     t + PH_FIT_V);
+  hipLaunchKernelGGL(kb_fit_x<FT>, dim3(GRID_FIT), dim3(FIT_THREADS), 0, st,
+                     runs, t + PH_FIT_X);
+  hipLaunchKernelGGL(kb_fit_v<FT>, dim3(GRID_FIT), dim3(FIT_THREADS), 0, st,
+                     runs, t + PH_FIT_V);
   hipLaunchKernelGGL(kb_ghost<FT>, dim3(GRID_FIT), dim3(256), 0, st, runs,
                      t + PH_GHOST);
   hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
@@ -853,15 +872,15 @@ void fill_desc(vp_ctx *c, void *fout, void *dst) {
   d.rec = c->at<double>(c->L.rec);
   d.qm = c->at<double>(c->L.qm);
   d.part = c->at<double>(c->L.part);
-  d.S = c->at<double>(c->L.S);
-  d.Mw = c->at<double>(c->L.Mw);
+  d.Mc = c->at<double>(c->L.Mc);
+  d.ctot = c->at<double>(c->L.ctot);
   d.Ml = c->at<double>(c->L.Ml);
   d.acc = c->at<double>(c->L.acc);
   d.dpart = c->at<double>(c->L.dpart);
   d.cnt = c->counts(0);
   d.lst = c->at<int>(c->L.lst);
   d.flags = c->at<int>(c->L.flags);
-  d.colcnt = c->at<int>(c->L.colcnt);
+  d.fcnt = c->at<int>(c->L.fcnt);
   d.ovf = c->at<unsigned long long>(c->L.ovf);
   d.F = c->at<FT>(c->L.F);
   d.C = c->at<FT>(c->L.C);
@@ -904,6 +923,7 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
     if (sl.need_predict)
       add(PH_PRED, q, el_items, EA_PRED | EA_DRIFT | EA_REG | regb);
     add(PH_RECON, q, tiles, cur);
+    add(PH_FIELD, q, (k.nx + FIELD_WG - 1) / FIELD_WG, 0);
     const int step_after = sl.done + 1;
     const bool remap_due = c->p.n_s > 0 && step_after % c->p.n_s == 0;
     const bool finish = step_after == sl.nsteps;

@@ -495,10 +495,14 @@ __device__ __forceinline__ double W_kernel(double x) {
 
 // ------------------------------------------------------------- the field
 
-// Single workgroup: S (or rho) -> rho -> M -> cumulative mass M_left (256-
-// site chunks, sequential inside, carries sequential) -> a, a', a'' on the
-// indices [-4, nx + 3] (section 2.5, eq. acccomp; centred difference over
-// 2 dx).  Optional outputs rho_out and a/da/d2a on [0, nx).
+// Cumulative mass and force (section 2.5, eq. acccomp; a' as a centred
+// difference over 2 dx).  M_left is summed in 256-site chunks, sequentially
+// inside a chunk, and the chunk carries are added sequentially.  One
+// workgroup of 256 threads handles one chunk: it forms the column values
+// (sum of the row-group partials in increasing group order, or rho given
+// directly), the chunk's sequential prefix and its total; the last chunk
+// workgroup to finish adds the carries and writes M_left and a, a', a''
+// on the indices [-4, nx + 3] (plus optional copies on [0, nx)).
 __device__ __forceinline__ double Ml_at(const double *Ml, int nx, double Mtot,
                                         int i) {
   if (i < 0) return 0.0;
@@ -506,64 +510,117 @@ __device__ __forceinline__ double Ml_at(const double *Ml, int nx, double Mtot,
   return Ml[i];
 }
 
-// The field computation of one workgroup (any size): `in` holds S (column
-// sums) or rho; ATOMIC_IN reads it with device-coherent loads (used when
-// other workgroups of the same kernel wrote it).  The 256-site chunks of
-// the cumulative sum go through LDS `stage` (stage_n doubles, a multiple of
-// 256) in rounds: all threads fill it, one thread per chunk runs the
-// sequential sum on it, all threads write it back.
-template <bool ATOMIC_IN>
-__device__ __forceinline__ void field_wg(
-    const KP &p, const double *__restrict__ in, int in_is_rho,
-    double *__restrict__ Ml, double *__restrict__ acc,
-    double *__restrict__ rho_out, double *__restrict__ a_out,
-    double *__restrict__ da_out, double *__restrict__ d2a_out, double *tot,
-    double *car, double *stage, int stage_n) {
-  const int nx = p.nx, tid = threadIdx.x, nt = blockDim.x;
-  for (int r0 = 0; r0 < nx; r0 += stage_n) {
-    const int rn = min(stage_n, nx - r0);
-    for (int q = tid; q < rn; q += nt) {
-      const int i = r0 + q;
-      double x;
-      if (ATOMIC_IN)
-        x = __longlong_as_double((long long)__hip_atomic_load(
-            reinterpret_cast<const unsigned long long *>(in) + i,
-            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      else
-        x = in[i];
-      const double rho = in_is_rho ? x : p.dv * x;
-      if (rho_out) rho_out[i] = rho;
-      stage[q] = p.dx * rho;
-    }
-    __syncthreads();
-    for (int c = tid; c * 256 < rn; c += nt) {
-      const int q1 = min(rn, c * 256 + 256);
-      double s = 0.0;
-      for (int q = c * 256; q < q1; ++q) {
-        s += stage[q];
-        stage[q] = s;
+constexpr int FIELD_CHUNKS = 1024;  // up to 262144 columns
+constexpr int FIELD_WG = 256;
+
+struct FieldArgs {
+  const double *in;   // row-group partials [ngy][nx] or rho [nx]
+  int ngy;            // number of row groups (partials), 0 when in is rho
+  int in_is_rho;
+  double *Mc;         // chunk-local prefix [nx]
+  double *ctot;       // chunk totals [nch]
+  int *fcnt;          // finished-chunk counter (zero between launches)
+  double *Ml;         // cumulative mass [nx]
+  double *acc;        // a, a', a'' on [-4, nx + 3]
+  double *rho_out, *a_out, *da_out, *d2a_out;  // optional
+};
+
+__device__ __forceinline__ double ld_coherent(const double *q) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      reinterpret_cast<const unsigned long long *>(q), __ATOMIC_RELAXED,
+      __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// LDS of one field workgroup
+struct FieldLds {
+  double stage[FIELD_WG];
+  double car[FIELD_CHUNKS];
+  int last;
+};
+
+__device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
+                                            int c, FieldLds &L) {
+  const int nx = p.nx, tid = threadIdx.x;
+  const int nch = (nx + FIELD_WG - 1) / FIELD_WG;
+  const int i0 = c * FIELD_WG, n = min(FIELD_WG, nx - i0);
+  if (tid < n) {
+    const int i = i0 + tid;
+    double x;
+    if (A.ngy > 0) {
+      // increasing group order; loads issued 16 ahead of the additions
+      x = 0.0;
+      const double *col = A.in + i;
+      int g = 0;
+      for (; g + 16 <= A.ngy; g += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = col[(size_t)(g + u) * nx];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x += v[u];
       }
-      tot[(r0 >> 8) + c] = s;
+      for (; g < A.ngy; ++g) x += col[(size_t)g * nx];
+    } else {
+      x = A.in[i];
     }
-    __syncthreads();
-    for (int q = tid; q < rn; q += nt) Ml[r0 + q] = stage[q];
-    __syncthreads();
+    const double rho = A.in_is_rho ? x : p.dv * x;
+    if (A.rho_out) A.rho_out[i] = rho;
+    L.stage[tid] = p.dx * rho;
   }
-  const int nch = (nx + 255) / 256;
+  __syncthreads();
+  if (tid == 0) {
+    // sequential prefix of the chunk, loads batched ahead of the chain
+    double s = 0.0;
+    const int nb = n & ~15;
+    for (int q0 = 0; q0 < nb; q0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = L.stage[q0 + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        s += v[u];
+        v[u] = s;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) L.stage[q0 + u] = v[u];
+    }
+    for (int q = nb; q < n; ++q) {
+      s += L.stage[q];
+      L.stage[q] = s;
+    }
+    A.ctot[c] = s;
+  }
+  __syncthreads();
+  // one wavefront publishes the chunk and takes the release/acquire count
+  if (tid < 64) {
+    for (int q = tid; q < n; q += 64) A.Mc[i0 + q] = L.stage[q];
+    if (tid == 0) {
+      const int old = __hip_atomic_fetch_add(A.fcnt, 1, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      L.last = (old == nch - 1);
+    }
+  }
+  __syncthreads();
+  if (!L.last) return;
+  // the last chunk: carries, M_left, force
+  for (int k = tid; k < nch; k += FIELD_WG) L.car[k] = ld_coherent(A.ctot + k);
+  __syncthreads();
   if (tid == 0) {
     double carry = 0.0;
-    for (int c = 0; c < nch; ++c) {
-      car[c] = carry;
-      carry = carry + tot[c];
+    for (int k = 0; k < nch; ++k) {
+      const double t = L.car[k];
+      L.car[k] = carry;
+      carry = carry + t;
     }
   }
   __syncthreads();
-  for (int i = tid; i < nx; i += nt) Ml[i] = car[i >> 8] + Ml[i];
+  for (int i = tid; i < nx; i += FIELD_WG)
+    A.Ml[i] = L.car[i / FIELD_WG] + ld_coherent(A.Mc + i);
   __syncthreads();
+  const double *Ml = A.Ml;
   const double Mtot = Ml[nx - 1];
   const int n8 = nx + 8;
   const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
-  for (int q = tid; q < n8; q += nt) {
+  for (int q = tid; q < n8; q += FIELD_WG) {
     const int i = q - 4;
     const double am = p.G * ((Mtot - Ml_at(Ml, nx, Mtot, i - 1)) -
                              Ml_at(Ml, nx, Mtot, i - 2));
@@ -573,29 +630,22 @@ __device__ __forceinline__ void field_wg(
                              Ml_at(Ml, nx, Mtot, i));
     const double da = (ap - am) / two_dx;
     const double d2a = ((ap + am) - 2.0 * a0) / dx2;
-    acc[q] = a0;
-    acc[n8 + q] = da;
-    acc[2 * n8 + q] = d2a;
-    if (a_out && i >= 0 && i < nx) {
-      a_out[i] = a0;
-      da_out[i] = da;
-      d2a_out[i] = d2a;
+    A.acc[q] = a0;
+    A.acc[n8 + q] = da;
+    A.acc[2 * n8 + q] = d2a;
+    if (A.a_out && i >= 0 && i < nx) {
+      A.a_out[i] = a0;
+      A.da_out[i] = da;
+      A.d2a_out[i] = d2a;
     }
   }
+  if (tid == 0)
+    __hip_atomic_store(A.fcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-constexpr int FIELD_CHUNKS = 1024;  // up to 262144 columns
-
-__global__ __launch_bounds__(1024) void k_field(
-    KP p, const double *__restrict__ in, int in_is_rho,
-    double *__restrict__ Ml, double *__restrict__ acc,
-    double *__restrict__ rho_out, double *__restrict__ a_out,
-    double *__restrict__ da_out, double *__restrict__ d2a_out) {
-  __shared__ double tot[FIELD_CHUNKS];
-  __shared__ double car[FIELD_CHUNKS];
-  __shared__ double stage[4096];
-  field_wg<false>(p, in, in_is_rho, Ml, acc, rho_out, a_out, da_out, d2a_out,
-                  tot, car, stage, 4096);
+__global__ __launch_bounds__(FIELD_WG) void k_field(KP p, FieldArgs A) {
+  __shared__ FieldLds L;
+  field_chunk(p, A, blockIdx.x, L);
 }
 
 // ------------------------------------------------------- reconstruction
@@ -603,24 +653,20 @@ __global__ __launch_bounds__(1024) void k_field(
 // One workgroup = 8 wavefronts stacked in v; one wavefront = one 8x8-site
 // query block (lane -> site: x = lane & 7, v = lane >> 3).  The workgroup
 // covers 8 columns x 64 rows, the row group of the fixed column-sum order.
-// In the density modes the last workgroup of each column block adds the
-// row-group partials (in increasing group order) into S, and the last of
-// those computes the force for the whole grid (field_wg), so one launch
-// covers density projection and Poisson solve.
+// In the density modes each workgroup writes the 8 column partials of its
+// row group (sequential over the 64 rows); the field kernel adds them in
+// increasing group order.  No workgroup waits on another, so the launch
+// needs no device-scope synchronisation.
 template <typename FT, int MODE>
 __device__ __forceinline__ void recon_tile(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
     const int *__restrict__ cnt,
     const int *__restrict__ lst, const int *__restrict__ flags,
-    const FT *__restrict__ F, double *__restrict__ part,
-    int *__restrict__ colcnt, double *__restrict__ S, FT *__restrict__ fout,
+    const FT *__restrict__ F, double *__restrict__ part, FT *__restrict__ fout,
     int *__restrict__ aout, double *__restrict__ dpart,
-    unsigned long long *__restrict__ ovf, int *__restrict__ donecnt,
-    double *__restrict__ Mw, double *__restrict__ Ml, double *__restrict__ acc,
-    double *__restrict__ rho_out, const int bx, const int gy) {
+    unsigned long long *__restrict__ ovf, const int bx, const int gy) {
   __shared__ double sf[512];
   __shared__ double sk[512];
-  __shared__ int s_last;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int bv = 8 * (gy - p.obv) + p.obv + w;
@@ -678,52 +724,13 @@ __device__ __forceinline__ void recon_tile(
       dpart[2 * wg + 1] = se[0];
     }
   }
-  if (w == 0) {
+  if (w == 0 && lane < 8) {
     // column partial of this row group: sequential over the 64 rows
     const int ic = p.ox + 8 * (bx - p.obx) + lane;
-    if (lane < 8) {
-      double s = 0.0;
-      for (int k = 0; k < 64; ++k) s += sf[(k >> 3) * 64 + (k & 7) * 8 + lane];
-      if (ic >= 0 && ic < p.nx) part[(size_t)gy * p.nx + ic] = s;
-    }
-    // the last workgroup of this column block adds the row-group partials
-    int last = 0;
-    if (lane == 0) {
-      const int old = __hip_atomic_fetch_add(&colcnt[bx], 1, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-      last = (old == p.ngy - 1);
-    }
-    last = __shfl(last, 0);
-    int lastall = 0;
-    if (last) {
-      if (lane < 8 && ic >= 0 && ic < p.nx) {
-        const unsigned long long *pu =
-            reinterpret_cast<const unsigned long long *>(part);
-        double s = 0.0;
-        for (int g = 0; g < p.ngy; ++g)
-          s += __longlong_as_double((long long)__hip_atomic_load(
-              pu + (size_t)g * p.nx + ic, __ATOMIC_RELAXED,
-              __HIP_MEMORY_SCOPE_AGENT));
-        S[ic] = s;
-      }
-      if (lane == 0) {
-        __hip_atomic_store(&colcnt[bx], 0, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        // the last column block to finish computes the field
-        const int old = __hip_atomic_fetch_add(donecnt, 1, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        lastall = (old == p.nbx - 1);
-      }
-    }
-    if (lane == 0) s_last = lastall;
+    double s = 0.0;
+    for (int k = 0; k < 64; ++k) s += sf[(k >> 3) * 64 + (k & 7) * 8 + lane];
+    if (ic >= 0 && ic < p.nx) part[(size_t)gy * p.nx + ic] = s;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __shared__ double stage[1024];
-  field_wg<true>(p, S, 0, Ml, acc, rho_out, nullptr, nullptr, nullptr, sf, sk,
-                 stage, 1024);
-  if (threadIdx.x == 0)
-    __hip_atomic_store(donecnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename FT, int MODE>
@@ -731,16 +738,12 @@ __global__ __launch_bounds__(512) void k_recon(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
     const int *__restrict__ cnt,
     const int *__restrict__ lst, const int *__restrict__ flags,
-    const FT *__restrict__ F, double *__restrict__ part,
-    int *__restrict__ colcnt, double *__restrict__ S, FT *__restrict__ fout,
+    const FT *__restrict__ F, double *__restrict__ part, FT *__restrict__ fout,
     int *__restrict__ aout, double *__restrict__ dpart,
-    unsigned long long *__restrict__ ovf, int *__restrict__ donecnt,
-    double *__restrict__ Mw, double *__restrict__ Ml, double *__restrict__ acc,
-    double *__restrict__ rho_out) {
+    unsigned long long *__restrict__ ovf) {
   const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
-  recon_tile<FT, MODE>(p, rec, qm, cnt, lst, flags, F, part, colcnt, S, fout,
-                       aout, dpart, ovf, donecnt, Mw, Ml, acc, rho_out,
-                       t % p.nbx, t / p.nbx);
+  recon_tile<FT, MODE>(p, rec, qm, cnt, lst, flags, F, part, fout, aout, dpart,
+                       ovf, t % p.nbx, t / p.nbx);
 }
 
 // Resampling value at every site (section 2.3.2): nearest element, the
@@ -895,135 +898,285 @@ __global__ __launch_bounds__(1024) void k_diag(
 
 // ------------------------------------------------------------- the spline
 
-// Tridiagonal (1, 4, 1) solve with end rows (4, 2) / (2, 4) along x for
-// every row (Thomas elimination; the row-independent pivots cp and 1/den are
-// precomputed).  One thread per row; the recurrence is strictly sequential
-// along the row, so each thread reads its row 16 values at a time (one
-// memory round trip per 16 sites) and runs the recurrence on registers.
-constexpr int FIT_CH = 16;
+// Tridiagonal (1, 4, 1) solves with end rows (4, 2) / (2, 4) (Thomas
+// elimination; the pivots cp and 1/den depend only on the position and are
+// precomputed), along x for every row and then along v for every column.
+// The recurrence is strictly sequential along a line, so a workgroup owns
+// 64 lines: wavefront 0 runs the 64 recurrences (lane = line) out of LDS,
+// while wavefronts 1-3 move tiles of 64 lines x TW positions between HBM
+// and a ring of three LDS tiles with coalesced accesses (the next tile is
+// loaded while the current one is solved, the previous one is written
+// back).  Forward sweep, then back substitution over the tiles in reverse.
+constexpr int FIT_LINES = 64;
+constexpr int FIT_THREADS = 256;
+constexpr int FIT_MOVERS = FIT_THREADS - 64;
+constexpr int FIT_NB = 3;
 
+template <typename FT>
+struct FitLds {
+  static constexpr int TW = 256 / (int)sizeof(FT);  // positions per tile
+  static constexpr int LP = FIT_LINES + 1;           // LDS pitch of a position
+  static constexpr int MR = (FIT_LINES * TW + FIT_MOVERS - 1) / FIT_MOVERS;
+  FT buf[FIT_NB][TW * LP];
+  FT coef[FIT_NB][TW];
+};
+
+// Geometry of one pass: element (line l, position i) lives at
+// base[l * ls + i * ps]; LINE_CONTIG says ls == 1 (columns), else ps == 1.
+template <typename FT>
+struct FitLine {
+  const FT *in;
+  FT *out;
+  long in_ls, in_ps, out_ls, out_ps;
+  const FT *coef;  // 1/den (forward) or cp (backward), per position
+  int n;           // positions
+  int nl;          // lines of this workgroup (<= 64)
+};
+
+template <typename FT, bool LINE_CONTIG>
+__device__ __forceinline__ void fit_map(int e, int &l, int &k) {
+  constexpr int TW = FitLds<FT>::TW;
+  if (LINE_CONTIG) {
+    k = e / FIT_LINES;
+    l = e % FIT_LINES;
+  } else {
+    l = e / TW;
+    k = e % TW;
+  }
+}
+
+template <typename FT, bool LINE_CONTIG>
+__device__ __forceinline__ void fit_load(const FitLine<FT> &G, int i0,
+                                         FT (&r)[FitLds<FT>::MR]) {
+  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR;
+  const int mt = (int)threadIdx.x - 64;
+  if (G.nl == FIT_LINES && i0 + TW <= G.n) {
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      const int e = min(mt + q * FIT_MOVERS, FIT_LINES * TW - 1);
+      int l, k;
+      fit_map<FT, LINE_CONTIG>(e, l, k);
+      r[q] = G.in[l * G.in_ls + (long)(i0 + k) * G.in_ps];
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    const int e = mt + q * FIT_MOVERS;
+    int l, k;
+    fit_map<FT, LINE_CONTIG>(e, l, k);
+    const bool ok = e < FIT_LINES * TW && l < G.nl && i0 + k < G.n;
+    r[q] = ok ? G.in[l * G.in_ls + (long)(i0 + k) * G.in_ps] : (FT)0;
+  }
+}
+
+template <typename FT, bool LINE_CONTIG>
+__device__ __forceinline__ void fit_put(const FitLine<FT> &G, int i0,
+                                        const FT (&r)[FitLds<FT>::MR], FT *buf,
+                                        FT *coef) {
+  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR, LP = FitLds<FT>::LP;
+  const int mt = (int)threadIdx.x - 64;
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    const int e = mt + q * FIT_MOVERS;
+    int l, k;
+    fit_map<FT, LINE_CONTIG>(e, l, k);
+    if (e < FIT_LINES * TW) buf[k * LP + l] = r[q];
+  }
+  if (mt < TW) coef[mt] = (i0 + mt < G.n) ? G.coef[i0 + mt] : (FT)0;
+}
+
+template <typename FT, bool LINE_CONTIG>
+__device__ __forceinline__ void fit_store(const FitLine<FT> &G, int i0,
+                                          const FT *buf) {
+  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR, LP = FitLds<FT>::LP;
+  const int mt = (int)threadIdx.x - 64;
+  const bool full = G.nl == FIT_LINES && i0 + TW <= G.n;
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    const int e = mt + q * FIT_MOVERS;
+    int l, k;
+    fit_map<FT, LINE_CONTIG>(e, l, k);
+    if (e < FIT_LINES * TW && (full || (l < G.nl && i0 + k < G.n)))
+      G.out[l * G.out_ls + (long)(i0 + k) * G.out_ps] = buf[k * LP + l];
+  }
+}
+
+// One sweep over all tiles.  BACK = false: forward elimination
+// d_i = (6 f_i - s_i d_{i-1}) / den_i with s_i = 2 at the last position,
+// else 1 (d_{-1} = 0 gives the first row exactly).  BACK = true: back
+// substitution c_i = d_i - cp_i c_{i+1} from the last position (c_n = 0
+// gives c_{n-1} = d_{n-1} exactly).  GHOST: also write the mirror rows
+// c(-1) = c(1) and c(n) = c(n - 2) of every line.
+template <typename FT, bool LINE_CONTIG, bool BACK, bool GHOST>
+__device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
+                                          FitLds<FT> &S) {
+  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR, LP = FitLds<FT>::LP;
+  const int n = G.n;
+  const int nt = (n + TW - 1) / TW;
+  const bool mover = threadIdx.x >= 64;
+  const int lane = threadIdx.x & 63;
+  // tile t of the sweep order starts at position tile_i0(t)
+  auto tile_i0 = [&](int t) { return (BACK ? nt - 1 - t : t) * TW; };
+  FT r[MR];
+  if (mover) {
+    fit_load<FT, LINE_CONTIG>(G, tile_i0(0), r);
+    fit_put<FT, LINE_CONTIG>(G, tile_i0(0), r, S.buf[0], S.coef[0]);
+    if (nt > 1) fit_load<FT, LINE_CONTIG>(G, tile_i0(1), r);
+  }
+  __syncthreads();
+  FT acc = (FT)0;
+  for (int t = 0; t < nt; ++t) {
+    const int b = t % FIT_NB;
+    if (!mover) {
+      const int i0 = tile_i0(t);
+      const int kn = min(TW, n - i0);
+      FT *col = S.buf[b] + lane;
+      const FT *cf = S.coef[b];
+      // positions [0, kb) in unguarded blocks of 16; the tile's remainder
+      // (and the last position of the line, whose sub-diagonal is 2) alone
+      const int kb = (i0 + kn == n) ? ((kn - 1) & ~15) : kn;
+      if (!BACK) {
+        for (int k0 = 0; k0 < kb; k0 += 16) {
+          FT v[16], c[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            v[u] = col[(k0 + u) * LP];
+            c[u] = cf[k0 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            acc = ((FT)6 * v[u] - acc) * c[u];
+            v[u] = acc;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) col[(k0 + u) * LP] = v[u];
+        }
+        for (int k = kb; k < kn; ++k) {
+          const FT sd = (i0 + k == n - 1) ? (FT)2 * acc : acc;
+          acc = ((FT)6 * col[k * LP] - sd) * cf[k];
+          col[k * LP] = acc;
+        }
+      } else {
+        auto ghost = [&](int i) {
+          if (GHOST && lane < G.nl) {
+            if (i == 1) G.out[lane * G.out_ls - G.out_ps] = acc;
+            if (i == n - 2) G.out[lane * G.out_ls + (long)n * G.out_ps] = acc;
+          }
+        };
+        for (int k = kn - 1; k >= kb; --k) {
+          acc = col[k * LP] - cf[k] * acc;
+          col[k * LP] = acc;
+          ghost(i0 + k);
+        }
+        for (int k0 = kb - 16; k0 >= 0; k0 -= 16) {
+          FT v[16], c[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            v[u] = col[(k0 + u) * LP];
+            c[u] = cf[k0 + u];
+          }
+#pragma unroll
+          for (int u = 15; u >= 0; --u) {
+            acc = v[u] - c[u] * acc;
+            v[u] = acc;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) col[(k0 + u) * LP] = v[u];
+          if (GHOST && (i0 + k0 <= 1 || i0 + k0 + 15 >= n - 2)) {
+            // rare: recover the two mirrored values from the block
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+              const int i = i0 + k0 + u;
+              if (lane < G.nl && i == 1) G.out[lane * G.out_ls - G.out_ps] = v[u];
+              if (lane < G.nl && i == n - 2)
+                G.out[lane * G.out_ls + (long)n * G.out_ps] = v[u];
+            }
+          }
+        }
+      }
+    } else {
+      if (t >= 1)
+        fit_store<FT, LINE_CONTIG>(G, tile_i0(t - 1), S.buf[(t - 1) % FIT_NB]);
+      if (t + 1 < nt) {
+        fit_put<FT, LINE_CONTIG>(G, tile_i0(t + 1), r, S.buf[(t + 1) % FIT_NB],
+                                 S.coef[(t + 1) % FIT_NB]);
+        if (t + 2 < nt) fit_load<FT, LINE_CONTIG>(G, tile_i0(t + 2), r);
+      }
+    }
+    __syncthreads();
+  }
+  if (mover)
+    fit_store<FT, LINE_CONTIG>(G, tile_i0(nt - 1), S.buf[(nt - 1) % FIT_NB]);
+  __syncthreads();
+}
+
+// Solve along x for rows [64 chunk, 64 chunk + 64): F (padded) -> T.
 template <typename FT>
 __device__ __forceinline__ void fit_x_rows(const KP &p, const FT *__restrict__ F,
                                           FT *__restrict__ T,
                                           const FT *__restrict__ cpx,
                                           const FT *__restrict__ rix,
-                                          const int chunk) {
-  const int j = chunk * 64 + threadIdx.x;
-  const int nx = p.nx;
-  if (j >= p.nv) return;
-  const FT *Fr = F + (long)(j + PV) * p.pitch + PX;
-  FT *Tr = T + (size_t)j * nx;
-  FT dp = (FT)0;
-  // forward sweep
-  for (int i0 = 0; i0 < nx; i0 += FIT_CH) {
-    FT v[FIT_CH];
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k) v[k] = (i0 + k < nx) ? Fr[i0 + k] : (FT)0;
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k) {
-      const int i = i0 + k;
-      if (i >= nx) break;
-      if (i == 0) {
-        dp = ((FT)6 * v[k]) * rix[0];
-      } else {
-        const FT sub = (i == nx - 1) ? (FT)2 : (FT)1;
-        dp = ((FT)6 * v[k] - sub * dp) * rix[i];
-      }
-      v[k] = dp;
-    }
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k)
-      if (i0 + k < nx) Tr[i0 + k] = v[k];
-  }
-  // back substitution, chunks in reverse
-  FT out = (FT)0;
-  const int last0 = ((nx - 1) / FIT_CH) * FIT_CH;
-  for (int i0 = last0; i0 >= 0; i0 -= FIT_CH) {
-    FT v[FIT_CH];
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k) v[k] = (i0 + k < nx) ? Tr[i0 + k] : (FT)0;
-#pragma unroll
-    for (int k = FIT_CH - 1; k >= 0; --k) {
-      const int i = i0 + k;
-      if (i >= nx) continue;
-      out = (i == nx - 1) ? v[k] : v[k] - cpx[i] * out;
-      v[k] = out;
-    }
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k)
-      if (i0 + k < nx) Tr[i0 + k] = v[k];
-  }
+                                          const int chunk, FitLds<FT> &S) {
+  const int j0 = chunk * FIT_LINES;
+  FitLine<FT> G;
+  G.n = p.nx;
+  G.nl = min(FIT_LINES, p.nv - j0);
+  G.in = F + (long)(j0 + PV) * p.pitch + PX;
+  G.in_ls = p.pitch;
+  G.in_ps = 1;
+  G.out = T + (size_t)j0 * p.nx;
+  G.out_ls = p.nx;
+  G.out_ps = 1;
+  G.coef = rix;
+  fit_sweep<FT, false, false, false>(G, S);
+  G.in = G.out;
+  G.in_ls = G.out_ls;
+  G.coef = cpx;
+  fit_sweep<FT, false, true, false>(G, S);
 }
 
-template <typename FT>
-__global__ __launch_bounds__(64) void k_fit_x(KP p, const FT *__restrict__ F,
-                                              FT *__restrict__ T,
-                                              const FT *__restrict__ cpx,
-                                              const FT *__restrict__ rix) {
-  fit_x_rows<FT>(p, F, T, cpx, rix, blockIdx.x);
-}
-
-
-// The same solve along v for every column (one thread per column: rows are
-// read and written coalesced, 16 rows per memory round trip), written into
-// C with mirror ghost rows.
+// Solve along v for columns [64 chunk, 64 chunk + 64): T -> C (padded, with
+// the mirror ghost rows).
 template <typename FT>
 __device__ __forceinline__ void fit_v_cols(const KP &p, const FT *__restrict__ T,
                                           FT *__restrict__ C,
                                           const FT *__restrict__ cpv,
                                           const FT *__restrict__ riv,
-                                          const int chunk) {
-  const int i = chunk * 64 + threadIdx.x;
-  const int nx = p.nx, nv = p.nv;
-  if (i >= nx) return;
-  const long pt = p.pitch;
-  FT *C0 = C + (long)PV * pt + PX + i;
-  FT dp = (FT)0;
-  for (int j0 = 0; j0 < nv; j0 += FIT_CH) {
-    FT v[FIT_CH];
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k)
-      v[k] = (j0 + k < nv) ? T[(size_t)(j0 + k) * nx + i] : (FT)0;
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k) {
-      const int j = j0 + k;
-      if (j >= nv) break;
-      if (j == 0) {
-        dp = ((FT)6 * v[k]) * riv[0];
-      } else {
-        const FT sub = (j == nv - 1) ? (FT)2 : (FT)1;
-        dp = ((FT)6 * v[k] - sub * dp) * riv[j];
-      }
-      C0[(long)j * pt] = dp;
-    }
-  }
-  FT out = (FT)0;
-  const int last0 = ((nv - 1) / FIT_CH) * FIT_CH;
-  for (int j0 = last0; j0 >= 0; j0 -= FIT_CH) {
-    FT v[FIT_CH];
-#pragma unroll
-    for (int k = 0; k < FIT_CH; ++k)
-      v[k] = (j0 + k < nv) ? C0[(long)(j0 + k) * pt] : (FT)0;
-#pragma unroll
-    for (int k = FIT_CH - 1; k >= 0; --k) {
-      const int j = j0 + k;
-      if (j >= nv) continue;
-      out = (j == nv - 1) ? v[k] : v[k] - cpv[j] * out;
-      C0[(long)j * pt] = out;
-    }
-  }
-  C0[-pt] = C0[pt];
-  C0[(long)nv * pt] = C0[(long)(nv - 2) * pt];
+                                          const int chunk, FitLds<FT> &S) {
+  const int i0 = chunk * FIT_LINES;
+  FitLine<FT> G;
+  G.n = p.nv;
+  G.nl = min(FIT_LINES, p.nx - i0);
+  G.in = T + i0;
+  G.in_ls = 1;
+  G.in_ps = p.nx;
+  G.out = C + (long)PV * p.pitch + PX + i0;
+  G.out_ls = 1;
+  G.out_ps = p.pitch;
+  G.coef = riv;
+  fit_sweep<FT, true, false, false>(G, S);
+  G.in = G.out;
+  G.in_ps = G.out_ps;
+  G.coef = cpv;
+  fit_sweep<FT, true, true, true>(G, S);
 }
 
 template <typename FT>
-__global__ __launch_bounds__(64) void k_fit_v(KP p, const FT *__restrict__ T,
-                                              FT *__restrict__ C,
-                                              const FT *__restrict__ cpv,
-                                              const FT *__restrict__ riv) {
-  fit_v_cols<FT>(p, T, C, cpv, riv, blockIdx.x);
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_x(
+    KP p, const FT *__restrict__ F, FT *__restrict__ T,
+    const FT *__restrict__ cpx, const FT *__restrict__ rix) {
+  __shared__ FitLds<FT> S;
+  fit_x_rows<FT>(p, F, T, cpx, rix, blockIdx.x, S);
 }
 
+template <typename FT>
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_v(
+    KP p, const FT *__restrict__ T, FT *__restrict__ C,
+    const FT *__restrict__ cpv, const FT *__restrict__ riv) {
+  __shared__ FitLds<FT> S;
+  fit_v_cols<FT>(p, T, C, cpv, riv, blockIdx.x, S);
+}
 
 // Mirror ghost columns c(-1, j) = c(1, j), c(nx, j) = c(nx - 2, j) for
 // j in [-1, nv] (corners follow from the ghost rows).
