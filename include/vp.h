@@ -71,7 +71,8 @@ extern "C" {
 #define VP_SCHEME_REMAP 1     /* W-blended Q_r + cubic B-spline */
 
 typedef struct vp_params {
-  int32_t nx, nv;      /* sites per axis, >= 8, multiples of sx / sv */
+  int32_t nx, nv;      /* sites per axis, >= 8, multiples of sx / sv;
+                          nx also a multiple of 4 */
   double x_min, x_max; /* phase-space box */
   double v_min, v_max;
   int32_t sx, sv;      /* element spacing in sites (dx_m = sx dx) */

@@ -44,7 +44,8 @@ struct Layout {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool params_ok(const vp_params *p) {
-  return p && p->nx >= 8 && p->nv >= 8 && p->sx >= 1 && p->sv >= 1 &&
+  return p && p->nx >= 8 && p->nv >= 8 && p->nx % 4 == 0 && p->sx >= 1 &&
+         p->sv >= 1 &&
          p->nx % p->sx == 0 && p->nv % p->sv == 0 && p->dt > 0.0 &&
          p->x_max > p->x_min && p->v_max > p->v_min && p->n_s >= 0 &&
          p->beta >= 0.0 && p->beta <= 0.5 &&

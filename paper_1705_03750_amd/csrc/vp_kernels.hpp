@@ -163,6 +163,33 @@ __device__ __forceinline__ void elem_kick(const KP &p,
 
 // Query record and block registration of one element; returns false when
 // the element is non-finite or det T <= 0 (flagged, not registered).
+// Can the validity window |A (P - P_m)| < (dx_m, dv_m) of an element hold a
+// site of query block (bxq, bvq)?  l = A (P - P_m) is linear in P, so over
+// the rectangle spanned by the block's sites it ranges over centre +- the
+// sum of |coefficient| x half-width in each component; the block is skipped
+// only when one component stays outside the window by more than a margin
+// that covers the rounding of l at the sites (relative to the magnitudes of
+// the products A_ij dP_j, which may cancel).
+__device__ __forceinline__ bool block_meets_window(
+    const KP &p, double X, double V, double axx, double axv, double avx,
+    double avv, int bxq, int bvq) {
+  const int i0 = p.ox + 8 * (bxq - p.obx), j0 = p.ov + 8 * (bvq - p.obv);
+  const int ia = max(0, i0), ib = min(p.nx - 1, i0 + 7);
+  const int ja = max(0, j0), jb = min(p.nv - 1, j0 + 7);
+  const double xa = site_x(p, ia), xb = site_x(p, ib);
+  const double va = site_v(p, ja), vb = site_v(p, jb);
+  const double cx = 0.5 * (xa + xb) - X, cv = 0.5 * (va + vb) - V;
+  const double hx = 0.5 * (xb - xa), hv = 0.5 * (vb - va);
+  const double mx = fabs(cx) + hx, mv = fabs(cv) + hv;
+  const double lxc = axx * cx + axv * cv;
+  const double rx = fabs(axx) * hx + fabs(axv) * hv;
+  const double lvc = avx * cx + avv * cv;
+  const double rv = fabs(avx) * hx + fabs(avv) * hv;
+  const double tx = 0x1p-36 * (fabs(axx) * (mx + 1.0) + fabs(axv) * (mv + 1.0) + p.dxm);
+  const double tv = 0x1p-36 * (fabs(avx) * (mx + 1.0) + fabs(avv) * (mv + 1.0) + p.dvm);
+  return fabs(lxc) - rx < p.dxm + tx && fabs(lvc) - rv < p.dvm + tv;
+}
+
 __device__ __forceinline__ void elem_record(
     const KP &p, const ElemState &s, int e, double *__restrict__ rec,
     double *__restrict__ qm, int *__restrict__ cnt, int *__restrict__ lst,
@@ -222,14 +249,22 @@ __device__ __forceinline__ void elem_record(
     return;
   }
   // slot claims are independent: issue them eight at a time and only then
-  // write the ids (one atomic round trip per eight blocks, not per block)
+  // write the ids (one atomic round trip per eight blocks, not per block).
+  // A block of the bounding box is listed only if the window can hold one
+  // of its sites (block_meets_window), so sheared windows do not fill the
+  // lists of the blocks their bounding box merely touches.
   const int wx = b1x - b0x + 1, nblk = wx * (b1v - b0v + 1);
   for (int q0 = 0; q0 < nblk; q0 += 8) {
     int bb[8], slot[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int q = q0 + k;
-      bb[k] = (q < nblk) ? (b0v + q / wx) * p.nbx + (b0x + q % wx) : -1;
+      bb[k] = -1;
+      if (q < nblk) {
+        const int bxq = b0x + q % wx, bvq = b0v + q / wx;
+        if (block_meets_window(p, s.x, s.v, axx, axv, avx, avv, bxq, bvq))
+          bb[k] = bvq * p.nbx + bxq;
+      }
       slot[k] = (bb[k] >= 0) ? atomicAdd(&cnt[bb[k]], 1) : p.cap;
     }
 #pragma unroll
@@ -903,26 +938,31 @@ __global__ __launch_bounds__(1024) void k_diag(
 // precomputed), along x for every row and then along v for every column.
 // The recurrence is strictly sequential along a line, so a workgroup owns
 // 64 lines: wavefront 0 runs the 64 recurrences (lane = line) out of LDS,
-// while wavefronts 1-3 move tiles of 64 lines x TW positions between HBM
+// while wavefronts 1-4 move tiles of 64 lines x TW positions between HBM
 // and a ring of three LDS tiles with coalesced accesses (the next tile is
 // loaded while the current one is solved, the previous one is written
 // back).  Forward sweep, then back substitution over the tiles in reverse.
 constexpr int FIT_LINES = 64;
-constexpr int FIT_THREADS = 256;
-constexpr int FIT_MOVERS = FIT_THREADS - 64;
+constexpr int FIT_MOVERS = 256;                 // wavefronts 1-4
+constexpr int FIT_THREADS = 64 + FIT_MOVERS;
 constexpr int FIT_NB = 3;
 
 template <typename FT>
 struct FitLds {
   static constexpr int TW = 256 / (int)sizeof(FT);  // positions per tile
   static constexpr int LP = FIT_LINES + 1;           // LDS pitch of a position
-  static constexpr int MR = (FIT_LINES * TW + FIT_MOVERS - 1) / FIT_MOVERS;
+  static constexpr int VEC = 16 / (int)sizeof(FT);   // elements per 16-B access
+  static constexpr int NV = FIT_LINES * TW / (VEC * FIT_MOVERS);  // per mover
   FT buf[FIT_NB][TW * LP];
   FT coef[FIT_NB][TW];
 };
+static_assert(FitLds<float>::NV * 4 * FIT_MOVERS == FIT_LINES * 64, "tile");
+static_assert(FitLds<double>::NV * 2 * FIT_MOVERS == FIT_LINES * 32, "tile");
 
 // Geometry of one pass: element (line l, position i) lives at
 // base[l * ls + i * ps]; LINE_CONTIG says ls == 1 (columns), else ps == 1.
+// Rows are 16-byte aligned and the contiguous extent is a multiple of 4, so
+// every 16-byte access lies wholly inside or wholly outside the data.
 template <typename FT>
 struct FitLine {
   const FT *in;
@@ -933,72 +973,107 @@ struct FitLine {
   int nl;          // lines of this workgroup (<= 64)
 };
 
+template <typename FT>
+struct FitVec {
+  static constexpr int VEC = FitLds<FT>::VEC;
+  FT v[VEC];
+};
+
+// Mover vector w covers VEC consecutive positions of one line (rows) or
+// VEC consecutive lines at one position (columns).
 template <typename FT, bool LINE_CONTIG>
-__device__ __forceinline__ void fit_map(int e, int &l, int &k) {
-  constexpr int TW = FitLds<FT>::TW;
+__device__ __forceinline__ void fit_map(int w, int &l, int &k) {
+  constexpr int TW = FitLds<FT>::TW, VEC = FitLds<FT>::VEC;
   if (LINE_CONTIG) {
-    k = e / FIT_LINES;
-    l = e % FIT_LINES;
+    k = w / (FIT_LINES / VEC);
+    l = (w % (FIT_LINES / VEC)) * VEC;
   } else {
-    l = e / TW;
-    k = e % TW;
+    l = w / (TW / VEC);
+    k = (w % (TW / VEC)) * VEC;
   }
 }
+
+template <typename FT>
+__device__ __forceinline__ void vec_ld(const FT *q, FitVec<FT> &r) {
+  if constexpr (sizeof(FT) == 4) {
+    const float4 t = *reinterpret_cast<const float4 *>(q);
+    r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+  } else {
+    const double2 t = *reinterpret_cast<const double2 *>(q);
+    r.v[0] = t.x; r.v[1] = t.y;
+  }
+}
+
+template <typename FT>
+__device__ __forceinline__ void vec_st(FT *q, const FitVec<FT> &r) {
+  if constexpr (sizeof(FT) == 4)
+    *reinterpret_cast<float4 *>(q) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  else
+    *reinterpret_cast<double2 *>(q) = make_double2(r.v[0], r.v[1]);
+}
+
+// Registers of one tile in flight: NV vectors + the tile's coefficient.
+template <typename FT>
+struct FitRegs {
+  FitVec<FT> x[FitLds<FT>::NV];
+  FT c;
+};
 
 template <typename FT, bool LINE_CONTIG>
 __device__ __forceinline__ void fit_load(const FitLine<FT> &G, int i0,
-                                         FT (&r)[FitLds<FT>::MR]) {
-  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR;
+                                         FitRegs<FT> &r) {
+  constexpr int NV = FitLds<FT>::NV, TW = FitLds<FT>::TW;
   const int mt = (int)threadIdx.x - 64;
-  if (G.nl == FIT_LINES && i0 + TW <= G.n) {
 #pragma unroll
-    for (int q = 0; q < MR; ++q) {
-      const int e = min(mt + q * FIT_MOVERS, FIT_LINES * TW - 1);
-      int l, k;
-      fit_map<FT, LINE_CONTIG>(e, l, k);
-      r[q] = G.in[l * G.in_ls + (long)(i0 + k) * G.in_ps];
-    }
-    return;
-  }
-#pragma unroll
-  for (int q = 0; q < MR; ++q) {
-    const int e = mt + q * FIT_MOVERS;
+  for (int q = 0; q < NV; ++q) {
     int l, k;
-    fit_map<FT, LINE_CONTIG>(e, l, k);
-    const bool ok = e < FIT_LINES * TW && l < G.nl && i0 + k < G.n;
-    r[q] = ok ? G.in[l * G.in_ls + (long)(i0 + k) * G.in_ps] : (FT)0;
+    fit_map<FT, LINE_CONTIG>(mt + q * FIT_MOVERS, l, k);
+    if (l < G.nl && i0 + k < G.n)
+      vec_ld(G.in + l * G.in_ls + (long)(i0 + k) * G.in_ps, r.x[q]);
+    else
+#pragma unroll
+      for (int u = 0; u < FitLds<FT>::VEC; ++u) r.x[q].v[u] = (FT)0;
   }
+  r.c = (mt < TW && i0 + mt < G.n) ? G.coef[i0 + mt] : (FT)0;
 }
 
 template <typename FT, bool LINE_CONTIG>
-__device__ __forceinline__ void fit_put(const FitLine<FT> &G, int i0,
-                                        const FT (&r)[FitLds<FT>::MR], FT *buf,
+__device__ __forceinline__ void fit_put(const FitRegs<FT> &r, FT *buf,
                                         FT *coef) {
-  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR, LP = FitLds<FT>::LP;
+  constexpr int NV = FitLds<FT>::NV, TW = FitLds<FT>::TW, LP = FitLds<FT>::LP,
+                VEC = FitLds<FT>::VEC;
   const int mt = (int)threadIdx.x - 64;
 #pragma unroll
-  for (int q = 0; q < MR; ++q) {
-    const int e = mt + q * FIT_MOVERS;
+  for (int q = 0; q < NV; ++q) {
     int l, k;
-    fit_map<FT, LINE_CONTIG>(e, l, k);
-    if (e < FIT_LINES * TW) buf[k * LP + l] = r[q];
+    fit_map<FT, LINE_CONTIG>(mt + q * FIT_MOVERS, l, k);
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+      if (LINE_CONTIG)
+        buf[k * LP + l + u] = r.x[q].v[u];
+      else
+        buf[(k + u) * LP + l] = r.x[q].v[u];
+    }
   }
-  if (mt < TW) coef[mt] = (i0 + mt < G.n) ? G.coef[i0 + mt] : (FT)0;
+  if (mt < TW) coef[mt] = r.c;
 }
 
 template <typename FT, bool LINE_CONTIG>
 __device__ __forceinline__ void fit_store(const FitLine<FT> &G, int i0,
                                           const FT *buf) {
-  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR, LP = FitLds<FT>::LP;
+  constexpr int NV = FitLds<FT>::NV, LP = FitLds<FT>::LP, VEC = FitLds<FT>::VEC;
   const int mt = (int)threadIdx.x - 64;
-  const bool full = G.nl == FIT_LINES && i0 + TW <= G.n;
 #pragma unroll
-  for (int q = 0; q < MR; ++q) {
-    const int e = mt + q * FIT_MOVERS;
+  for (int q = 0; q < NV; ++q) {
     int l, k;
-    fit_map<FT, LINE_CONTIG>(e, l, k);
-    if (e < FIT_LINES * TW && (full || (l < G.nl && i0 + k < G.n)))
-      G.out[l * G.out_ls + (long)(i0 + k) * G.out_ps] = buf[k * LP + l];
+    fit_map<FT, LINE_CONTIG>(mt + q * FIT_MOVERS, l, k);
+    if (l < G.nl && i0 + k < G.n) {
+      FitVec<FT> t;
+#pragma unroll
+      for (int u = 0; u < VEC; ++u)
+        t.v[u] = LINE_CONTIG ? buf[k * LP + l + u] : buf[(k + u) * LP + l];
+      vec_st(G.out + l * G.out_ls + (long)(i0 + k) * G.out_ps, t);
+    }
   }
 }
 
@@ -1011,20 +1086,30 @@ __device__ __forceinline__ void fit_store(const FitLine<FT> &G, int i0,
 template <typename FT, bool LINE_CONTIG, bool BACK, bool GHOST>
 __device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
                                           FitLds<FT> &S) {
-  constexpr int TW = FitLds<FT>::TW, MR = FitLds<FT>::MR, LP = FitLds<FT>::LP;
+  constexpr int TW = FitLds<FT>::TW, LP = FitLds<FT>::LP;
   const int n = G.n;
   const int nt = (n + TW - 1) / TW;
   const bool mover = threadIdx.x >= 64;
   const int lane = threadIdx.x & 63;
   // tile t of the sweep order starts at position tile_i0(t)
   auto tile_i0 = [&](int t) { return (BACK ? nt - 1 - t : t) * TW; };
-  FT r[MR];
+  // two register sets: tile u is loaded into set u % 2 three iterations
+  // before it is needed and put into LDS one iteration before
+  FitRegs<FT> ra, rb;
   if (mover) {
-    fit_load<FT, LINE_CONTIG>(G, tile_i0(0), r);
-    fit_put<FT, LINE_CONTIG>(G, tile_i0(0), r, S.buf[0], S.coef[0]);
-    if (nt > 1) fit_load<FT, LINE_CONTIG>(G, tile_i0(1), r);
+    fit_load<FT, LINE_CONTIG>(G, tile_i0(0), ra);
+    fit_put<FT, LINE_CONTIG>(ra, S.buf[0], S.coef[0]);
+    if (nt > 1) fit_load<FT, LINE_CONTIG>(G, tile_i0(1), rb);
+    if (nt > 2) fit_load<FT, LINE_CONTIG>(G, tile_i0(2), ra);
   }
   __syncthreads();
+  auto mover_step = [&](int t, FitRegs<FT> &rs) {
+    if (t + 1 < nt) {
+      fit_put<FT, LINE_CONTIG>(rs, S.buf[(t + 1) % FIT_NB],
+                               S.coef[(t + 1) % FIT_NB]);
+      if (t + 3 < nt) fit_load<FT, LINE_CONTIG>(G, tile_i0(t + 3), rs);
+    }
+  };
   FT acc = (FT)0;
   for (int t = 0; t < nt; ++t) {
     const int b = t % FIT_NB;
@@ -1098,11 +1183,10 @@ __device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
     } else {
       if (t >= 1)
         fit_store<FT, LINE_CONTIG>(G, tile_i0(t - 1), S.buf[(t - 1) % FIT_NB]);
-      if (t + 1 < nt) {
-        fit_put<FT, LINE_CONTIG>(G, tile_i0(t + 1), r, S.buf[(t + 1) % FIT_NB],
-                                 S.coef[(t + 1) % FIT_NB]);
-        if (t + 2 < nt) fit_load<FT, LINE_CONTIG>(G, tile_i0(t + 2), r);
-      }
+      if (t & 1)
+        mover_step(t, ra);
+      else
+        mover_step(t, rb);
     }
     __syncthreads();
   }

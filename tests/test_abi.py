@@ -40,6 +40,7 @@ def test_footprint_and_validation(vp):
     assert 3 * 2048 * 2048 * 8 < big < 8 * 2048 * 2048 * 8
     for bad in (dict(nx=250, sx=4, dt=1e-3),      # nx % sx
                 dict(nx=4, sx=1, dt=1e-3),        # too small
+                dict(nx=30, sx=3, dt=1e-3),       # nx % 4
                 dict(nx=64, sx=4, dt=0.0),        # dt <= 0
                 dict(nx=64, sx=4, dt=1e-3, x_min=1.0, x_max=1.0),
                 dict(nx=64, sx=4, dt=1e-3, n_s=-1),
