@@ -42,6 +42,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, FMA counted as 2
+FLOPS_PER_EVAL = 34             # one full candidate evaluation, FP64
+EVALS_PER_SITE = 4              # windows holding a site (2 per axis)
+
+
 def recon_algorithmic_bytes(n: int, s: int, fbytes: int) -> dict:
     """Bytes one launch of the transport reconstruction must move: F_ini
     read once, each element's query data (position, A, H: 12 doubles) read
@@ -54,6 +59,16 @@ def recon_algorithmic_bytes(n: int, s: int, fbytes: int) -> dict:
     b_p = ngy * n * 8
     return {"F_ini": b_f, "elements": b_e, "partials": b_p,
             "total": b_f + b_e + b_p}
+
+
+def recon_algorithmic_flops(n: int) -> float:
+    """FP64 flops one launch must do: every site lies in the validity
+    windows of 4 elements (half-width = element spacing, 2 per axis), and
+    each of them needs the full inverse map and distance (2 sub, 2 mul +
+    2 fma for l, 3 mul for the monomials, 2 x (mul + 2 fma) for u, 4 fma
+    for dQ, 2 mul + mul + fma for d^2: 34 flops).  The six-point
+    interpolation and the column sums are not counted."""
+    return float(n) * n * EVALS_PER_SITE * FLOPS_PER_EVAL
 
 
 def run_gpu(precision: str, cfg, f0, steps: int, warmup: int, prof: bool):
@@ -185,15 +200,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--cpu-threads", type=int,
                     default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-step-scale", type=float, default=0.1)
+    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-step-scale", type=float, default=0.25)
     ap.add_argument("--serve-occupancy", type=float, default=0.8)
-    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-cal", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (5x), "
                          "the reference for scaling rocprofv3 FETCH_SIZE / "
@@ -234,7 +249,9 @@ def main():
     ms_recon, n_recon = m["kernels"]["recon"]
     avg_s = ms_recon / n_recon / 1e3
     alg = recon_algorithmic_bytes(cfg.n, cfg.s, fb)
-    achieved = alg["total"] / avg_s / 1e9
+    flops = recon_algorithmic_flops(cfg.n)
+    achieved = flops / avg_s / 1e12
+    gbps = alg["total"] / avg_s / 1e9
     traffic = load_traffic("recon", main_prec)
     out = {
         "metric": METRIC,
@@ -255,13 +272,16 @@ def main():
                                "dt 5e-4, remap every 50 steps",
                    "grid": cfg.n, "element_stride": cfg.s, "dt": cfg.dt,
                    "n_s": cfg.n_s, "precision": main_prec},
-        "roofline": {"bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_recon (transport reconstruction + column "
-                               "sums)",
+        "roofline": {"bound": "alu", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "k_recon (nearest element, inverse map, "
+                               "six-point interpolation, column partials)",
                      "avg_launch_us": avg_s * 1e6,
-                     "algorithmic_bytes_per_launch": alg["total"]},
+                     "algorithmic_flops_per_launch": flops,
+                     "algorithmic_bytes_per_launch": alg["total"],
+                     "hbm_achieved_GBps": gbps,
+                     "hbm_frac": gbps / HBM_PEAK_GBS},
     }
     if "fp64" in res and main_prec != "fp64":
         f = res["fp64"]
@@ -271,7 +291,7 @@ def main():
                        "mixed_over_fp64": m["value"] / f["value"]}
     out["kernels_ms_per_step"] = {
         k: v[0] / args.steps for k, v in m["kernels"].items() if v[1]}
-    if args.serve:
+    if not args.no_serve and args.only is None:
         out["serving"] = serve_leg(args.serve_requests, args.serve_step_scale,
                                    seed=4, occupancy=args.serve_occupancy,
                                    max_active=64, pool_gb=8.0)
