@@ -26,11 +26,13 @@ namespace vpk {
 
 constexpr int PX = 16;  // x padding of F / C (values)
 constexpr int PV = 2;   // v padding of F / C (rows)
-constexpr int RS = 16;  // doubles per element query record (128 B)
+constexpr int RS = 12;  // doubles per element query record (96 B)
 constexpr int SPAN_LIMIT = 4096;  // max query blocks one element may enter
 
 enum {
-  R_X = 0, R_V, R_AXX, R_AXV, R_AVX, R_AVV, R_NAXX, R_NAXV, R_NAVX, R_NAVV,
+  R_X = 0, R_V, R_AXX, R_AXV, R_AVX, R_AVV,
+  // -H/2 (the off-diagonal term doubled): the map's -A/2 factor moved onto
+  // H, which scales every rounding step by an exact power of two
   R_HXXX, R_H2XXV, R_HXVV, R_HVXX, R_H2VXV, R_HVVV
 };
 enum {
@@ -208,16 +210,12 @@ __device__ __forceinline__ void elem_record(
   r[R_AXV] = axv;
   r[R_AVX] = avx;
   r[R_AVV] = avv;
-  r[R_NAXX] = -0.5 * axx;
-  r[R_NAXV] = -0.5 * axv;
-  r[R_NAVX] = -0.5 * avx;
-  r[R_NAVV] = -0.5 * avv;
-  r[R_HXXX] = s.hx0;
-  r[R_H2XXV] = 2.0 * s.hx1;
-  r[R_HXVV] = s.hx2;
-  r[R_HVXX] = s.hv0;
-  r[R_H2VXV] = 2.0 * s.hv1;
-  r[R_HVVV] = s.hv2;
+  r[R_HXXX] = -0.5 * s.hx0;
+  r[R_H2XXV] = -s.hx1;
+  r[R_HXVV] = -0.5 * s.hx2;
+  r[R_HVXX] = -0.5 * s.hv0;
+  r[R_H2VXV] = -s.hv1;
+  r[R_HVVV] = -0.5 * s.hv2;
   qm[2 * (size_t)e] = site_x(p, p.sx * k + p.sx / 2);
   qm[2 * (size_t)e + 1] = site_v(p, p.sv * l + p.sv / 2);
   // Eulerian reach of the validity window |A dP| < dx_m: |dP_x| <=
@@ -334,7 +332,10 @@ __global__ __launch_bounds__(256) void k_fill(T *__restrict__ a, long long n,
 // One candidate of the nearest-element query (sections 1 and 2.3): inverse
 // map of eq. (QofP) with l = A dP, validity |l| < element spacing, squared
 // Lagrangian distance of eq. (distdef) in element-spacing units; the best
-// is the smallest (d^2, id).  r is the candidate's record.
+// is the smallest (d^2, id).  r is the candidate's record.  With -H/2 in
+// the record, dQ = l + A u' with u'_c = l^T (-H_c/2) l, which equals
+// l - A u / 2 bit for bit (scaling by a power of two commutes with every
+// rounding step).
 template <typename R>
 __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
                                                 double xP, double vP,
@@ -347,8 +348,8 @@ __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
     const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
     const double ux = fma(r[R_HXXX], pxx, fma(r[R_H2XXV], pxv, r[R_HXVV] * pvv));
     const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
-    const double dqx = fma(r[R_NAXX], ux, fma(r[R_NAXV], uv, lx));
-    const double dqv = fma(r[R_NAVX], ux, fma(r[R_NAVV], uv, lv));
+    const double dqx = fma(r[R_AXX], ux, fma(r[R_AXV], uv, lx));
+    const double dqv = fma(r[R_AVX], ux, fma(r[R_AVV], uv, lv));
     const double zx = dqx * p.rx, zv = dqv * p.rv;
     const double d2 = fma(zx, zx, zv * zv);
     if (d2 < bd || (d2 == bd && e < best)) {
@@ -371,8 +372,8 @@ __device__ __forceinline__ void element_map(const KP &p,
   const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
   const double ux = fma(r[R_HXXX], pxx, fma(r[R_H2XXV], pxv, r[R_HXVV] * pvv));
   const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
-  dqx = fma(r[R_NAXX], ux, fma(r[R_NAXV], uv, lx));
-  dqv = fma(r[R_NAVX], ux, fma(r[R_NAVV], uv, lv));
+  dqx = fma(r[R_AXX], ux, fma(r[R_AXV], uv, lx));
+  dqv = fma(r[R_AVX], ux, fma(r[R_AVV], uv, lv));
 }
 
 struct Rec {
@@ -387,48 +388,61 @@ __device__ __forceinline__ void load_rec(const double *__restrict__ rec,
   for (int k = 0; k < RS; ++k) r.v[k] = q[k];
 }
 
-// Nearest element of (xP, vP) from the wave's block list (uniform over the
-// wavefront: a candidate's record is one 128-B scalar load, the next list
-// entry is requested a candidate ahead), or from all elements when the list
-// overflowed or an element was too wide to list.
+// Records staged per round in a wavefront's LDS area (QSTAGE * RS doubles).
+constexpr int QSTAGE = 20;
+constexpr int RPIECES = RS / 2;  // 16-byte pieces per record
+
+// Nearest element of (xP, vP) from the wave's block list, or from all
+// elements when the list overflowed or an element was too wide to list.
+// The list's records are brought into the wave's LDS area together (one
+// 16-byte piece per lane, about ten records per load instruction), so the
+// candidates cost one memory round trip per QSTAGE records instead of one
+// each; the candidate loop then reads them as uniform LDS broadcasts.
 __device__ __forceinline__ int query_block(
     const KP &p, const double *__restrict__ rec, const int *__restrict__ lst,
     int b, int n, bool scan_all, double xP, double vP, double &dqx,
-    double &dqv) {
+    double &dqv, double *stage) {
   double bd = __builtin_inf();
   int best = -1;
   dqx = 0.0;
   dqv = 0.0;
+  const int lane = threadIdx.x & 63;
   if (!scan_all) {
-    if (n <= 0) return best;
-    // list ids four at a time (one scalar load; rows are 16-int aligned and
-    // cap is a multiple of 16, so the read stays inside the row)
-    const int4 *L4 = reinterpret_cast<const int4 *>(lst + (size_t)b * p.cap);
-    int4 ids = L4[0];
-    for (int c0 = 0; c0 < n; c0 += 4) {
-      // the next four ids travel with the first record of this chunk
-      const int4 nxt = (c0 + 4 < n) ? L4[(c0 >> 2) + 1] : ids;
-      const int id4[4] = {ids.x, ids.y, ids.z, ids.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (c0 + k >= n) break;
-        const int e = id4[k];
+    const int *L = lst + (size_t)b * p.cap;
+    for (int c0 = 0; c0 < n; c0 += QSTAGE) {
+      const int m = min(QSTAGE, n - c0);
+      const int myid = (lane < m) ? L[c0 + lane] : 0;
+      // pieces lane and lane + 64 (QSTAGE * RPIECES <= 128): both loads
+      // are issued before either is stored
+      static_assert(QSTAGE * RPIECES <= 128, "two pieces per lane");
+      const int np = m * RPIECES;
+      const int ta = lane, tb = lane + 64;
+      const int ra = ta / RPIECES, rb = tb / RPIECES;
+      const int ida = __shfl(myid, ra), idb = __shfl(myid, min(rb, 63));
+      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+      if (ta < np)
+        va = *reinterpret_cast<const double2 *>(rec + (size_t)ida * RS +
+                                                2 * (ta - ra * RPIECES));
+      if (tb < np)
+        vb = *reinterpret_cast<const double2 *>(rec + (size_t)idb * RS +
+                                                2 * (tb - rb * RPIECES));
+      if (ta < np)
+        *reinterpret_cast<double2 *>(stage + 2 * ta) = va;
+      if (tb < np)
+        *reinterpret_cast<double2 *>(stage + 2 * tb) = vb;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int k = 0; k < m; ++k) {
+        const int e = __builtin_amdgcn_readlane(myid, k);
         Rec r;
-        load_rec(rec, e, r);
-        // All 16 values are wanted before the validity branch: one batch of
-        // scalar loads (one memory round trip) instead of a second batch
-        // inside the branch.  The empty statement emits no instruction.
-        __asm__ volatile("" ::"s"(r.v[0]), "s"(r.v[1]), "s"(r.v[2]),
-                         "s"(r.v[3]), "s"(r.v[4]), "s"(r.v[5]), "s"(r.v[6]),
-                         "s"(r.v[7]), "s"(r.v[8]), "s"(r.v[9]), "s"(r.v[10]),
-                         "s"(r.v[11]), "s"(r.v[12]), "s"(r.v[13]),
-                         "s"(r.v[14]), "s"(r.v[15]));
-        if (k == 0)
-          __asm__ volatile("" ::"s"(nxt.x), "s"(nxt.y), "s"(nxt.z),
-                           "s"(nxt.w));
+#pragma unroll
+        for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
         query_candidate(p, r, e, xP, vP, bd, best, dqx, dqv);
       }
-      ids = nxt;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   } else {
     for (int e = 0; e < p.E; ++e) {
@@ -702,6 +716,7 @@ __device__ __forceinline__ void recon_tile(
     unsigned long long *__restrict__ ovf, const int bx, const int gy) {
   __shared__ double sf[512];
   __shared__ double sk[512];
+  __shared__ __attribute__((aligned(16))) double qstage[8][QSTAGE * RS];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int bv = 8 * (gy - p.obv) + p.obv + w;
@@ -718,7 +733,8 @@ __device__ __forceinline__ void recon_tile(
     if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
     const double xP = site_x(p, i), vP = site_v(p, j);
     double dqx, dqv;
-    best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv);
+    best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv,
+                       qstage[w]);
     if (live && best >= 0) {
       const double Qx = qm[2 * (size_t)best] + dqx;
       const double Qv = qm[2 * (size_t)best + 1] + dqv;
@@ -793,6 +809,7 @@ __device__ __forceinline__ void remap_tile(
     const int *__restrict__ lst, const int *__restrict__ flags,
     const FT *__restrict__ C, FT *__restrict__ Fout,
     unsigned long long *__restrict__ ovf, const int bx, const int gy) {
+  __shared__ __attribute__((aligned(16))) double qstage[8][QSTAGE * RS];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int bv = 8 * (gy - p.obv) + p.obv + w;
@@ -806,7 +823,8 @@ __device__ __forceinline__ void remap_tile(
   if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
   const double xP = site_x(p, i), vP = site_v(p, j);
   double dqx, dqv;
-  const int best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv);
+  const int best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv,
+                               qstage[w]);
   if (!live) return;
   FT val = (FT)0;
   const bool ring = (i == 0 || j == 0 || i == p.nx - 1 || j == p.nv - 1);
