@@ -279,10 +279,15 @@ int launch_field(vp_ctx *c, const double *in, int from_part, double *rho_out,
   A.a_out = a_out;
   A.da_out = da_out;
   A.d2a_out = d2a_out;
-  const int nch = (c->k.nx + FIELD_WG - 1) / FIELD_WG;
-  hipLaunchKernelGGL(k_field, dim3(nch), dim3(FIELD_WG), 0, c->stream, c->k,
-                     A);
-  VP_LAUNCH_CHECK(c, "k_field");
+  if (c->k.nx <= FIELD1_MAX) {
+    hipLaunchKernelGGL(k_field1, dim3(1), dim3(1024), 0, c->stream, c->k, A);
+    VP_LAUNCH_CHECK(c, "k_field1");
+  } else {
+    const int nch = (c->k.nx + FIELD_WG - 1) / FIELD_WG;
+    hipLaunchKernelGGL(k_field, dim3(nch), dim3(FIELD_WG), 0, c->stream, c->k,
+                       A);
+    VP_LAUNCH_CHECK(c, "k_field");
+  }
   return VP_OK;
 }
 

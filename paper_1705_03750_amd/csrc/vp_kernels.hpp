@@ -697,6 +697,117 @@ __global__ __launch_bounds__(FIELD_WG) void k_field(KP p, FieldArgs A) {
   field_chunk(p, A, blockIdx.x, L);
 }
 
+// The same field in one workgroup of 1024 threads for grids of at most
+// FIELD1_MAX columns: no cross-workgroup hand-off, M_left stays in LDS.
+// Identical operations in identical order (column sums in increasing group
+// order, 256-site chunk prefixes, sequential carries).
+constexpr int FIELD1_MAX = 2048;
+
+__global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
+  __shared__ double M[FIELD1_MAX];
+  __shared__ double car[FIELD1_MAX / FIELD_WG];
+  const int nx = p.nx, tid = threadIdx.x;
+  const int nch = (nx + FIELD_WG - 1) / FIELD_WG;
+  // column values, two columns per thread, loads 16 groups ahead
+  {
+    double xs[2] = {0.0, 0.0};
+    const int i0 = tid, i1 = tid + 1024;
+    if (A.ngy > 0) {
+      for (int g0 = 0; g0 < A.ngy; g0 += 16) {
+        double v0[16], v1[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const bool g_ok = g0 + u < A.ngy;
+          v0[u] = (g_ok && i0 < nx) ? A.in[(size_t)(g0 + u) * nx + i0] : 0.0;
+          v1[u] = (g_ok && i1 < nx) ? A.in[(size_t)(g0 + u) * nx + i1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          if (g0 + u < A.ngy) {
+            xs[0] += v0[u];
+            xs[1] += v1[u];
+          }
+        }
+      }
+    } else {
+      if (i0 < nx) xs[0] = A.in[i0];
+      if (i1 < nx) xs[1] = A.in[i1];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int i = c ? i1 : i0;
+      if (i < nx) {
+        const double rho = A.in_is_rho ? xs[c] : p.dv * xs[c];
+        if (A.rho_out) A.rho_out[i] = rho;
+        M[i] = p.dx * rho;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < nch) {
+    // sequential prefix of chunk tid
+    const int q0c = tid * FIELD_WG, n = min(FIELD_WG, nx - q0c);
+    double *st = M + q0c;
+    double s = 0.0;
+    const int nb = n & ~15;
+    for (int q0 = 0; q0 < nb; q0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = st[q0 + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        s += v[u];
+        v[u] = s;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) st[q0 + u] = v[u];
+    }
+    for (int q = nb; q < n; ++q) {
+      s += st[q];
+      st[q] = s;
+    }
+    car[tid] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double carry = 0.0;
+    for (int k = 0; k < nch; ++k) {
+      const double t = car[k];
+      car[k] = carry;
+      carry = carry + t;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < nx; i += 1024) {
+    const double m = car[i / FIELD_WG] + M[i];
+    M[i] = m;
+    A.Ml[i] = m;
+  }
+  __syncthreads();
+  const double Mtot = M[nx - 1];
+  const int n8 = nx + 8;
+  const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
+  for (int q = tid; q < n8; q += 1024) {
+    const int i = q - 4;
+    const double am = p.G * ((Mtot - Ml_at(M, nx, Mtot, i - 1)) -
+                             Ml_at(M, nx, Mtot, i - 2));
+    const double a0 = p.G * ((Mtot - Ml_at(M, nx, Mtot, i)) -
+                             Ml_at(M, nx, Mtot, i - 1));
+    const double ap = p.G * ((Mtot - Ml_at(M, nx, Mtot, i + 1)) -
+                             Ml_at(M, nx, Mtot, i));
+    const double da = (ap - am) / two_dx;
+    const double d2a = ((ap + am) - 2.0 * a0) / dx2;
+    A.acc[q] = a0;
+    A.acc[n8 + q] = da;
+    A.acc[2 * n8 + q] = d2a;
+    if (A.a_out && i >= 0 && i < nx) {
+      A.a_out[i] = a0;
+      A.da_out[i] = da;
+      A.d2a_out[i] = d2a;
+    }
+  }
+}
+
 // ------------------------------------------------------- reconstruction
 
 // One workgroup = 8 wavefronts stacked in v; one wavefront = one 8x8-site

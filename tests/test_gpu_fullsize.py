@@ -1,0 +1,164 @@
+"""Parity at the benchmark sizes and launch configuration, and the
+degenerate inputs of the method.
+
+The 2048^2 halo workload (elements every 8th site) runs a full remap cycle
+on both sides and is compared element by element.  The 8192^2 and 16384^2
+workloads run a few steps: the FP64 engine is compared with the oracle on
+every element and on a seeded sample of sites (the oracle reconstructs the
+whole grid, the sample keeps the host-side comparison small), the mixed
+engine against the FP64 oracle on the same sample.  Degenerate cases: an
+all-zero distribution, one element per axis, the smallest grid.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def vp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_03750_amd as vp
+    vp.lib()
+    return vp
+
+
+def rel_linf(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = np.abs(b).max()
+    return float(np.abs(a - b).max() / scale) if scale > 0 else float(
+        np.abs(a - b).max())
+
+
+def run_pair(vp, orc, cfg, f0, precision="fp64"):
+    p = cfg.params()
+    p.pop("precision")
+    o = orc.Oracle(**p)
+    o.init_conditions(f0)
+    g = vp.VlasovRun(device="cuda:0", precision=precision, **p)
+    import torch
+    g.init_conditions(torch.as_tensor(f0, device="cuda:0"))
+    return o, g
+
+
+def sample_sites(n, count, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, n, count), rng.integers(0, n, count)
+
+
+def test_c2_full_size_fp64_remap_cycle(vp, orc):
+    """2048^2, s = 8: 50 steps (the remap at step 50 included)."""
+    cfg, f0 = W.config("c2_halos_2048")
+    o, g = run_pair(vp, orc, cfg, f0)
+    print(f"[c2 fp64] n={cfg.n} s={cfg.s} steps={cfg.n_s}", flush=True)
+    o.step(cfg.n_s)
+    g.step(cfg.n_s)
+    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    assert rel_linf(g.density().cpu().numpy(), o.density()) <= RTOL
+    # one more step away from the remap: the assignment of deformed elements
+    o.step(7)
+    g.step(7)
+    assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(False))
+    g.sync()
+
+
+def test_c2_full_size_mixed(vp, orc):
+    """Mixed precision at 2048^2 against the FP64 oracle: rel L2 on f
+    <= 1e-5 after 30 steps, and the assignment bit-exact given the same
+    element state."""
+    cfg, f0 = W.config("c2_halos_2048")
+    o, g = run_pair(vp, orc, cfg, f0, precision="mixed")
+    print(f"[c2 mixed] n={cfg.n} s={cfg.s} steps=30", flush=True)
+    o.step(30)
+    g.step(30)
+    f_ref = o.reconstruct_f()
+    f_gpu = g.reconstruct_f().cpu().numpy().astype(np.float64)
+    l2 = np.linalg.norm(f_gpu - f_ref) / np.linalg.norm(f_ref)
+    assert l2 <= 1e-5, l2
+    g.set_elements(o.get_elements())
+    assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(False))
+    g.sync()
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("name,steps", [("c3_halos_sheet_8192", 2),
+                                        ("c5_halos_cold_16384", 1)])
+def test_large_grids_sampled(vp, orc, name, steps):
+    """8192^2 (s = 8) and 16384^2 (s = 16): every element bitwise, f on a
+    seeded sample of 2^18 sites; mixed precision on the same sample."""
+    import time
+    import torch
+    t0 = time.time()
+
+    def say(msg):
+        print(f"[{name}] {msg} at {time.time() - t0:.1f} s", flush=True)
+
+    cfg, f0 = W.config(name)
+    say(f"inputs n={cfg.n} s={cfg.s} steps={steps}")
+    o, g = run_pair(vp, orc, cfg, f0)
+    say("both sides initialised")
+    o.step(steps)
+    say("oracle stepped")
+    g.step(steps)
+    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    j, i = sample_sites(cfg.n, 1 << 18, seed=cfg.seed)
+    ref = o.reconstruct_f()[j, i]
+    say("oracle reconstructed")
+    jt = torch.as_tensor(j, device="cuda:0")
+    it = torch.as_tensor(i, device="cuda:0")
+    got = g.reconstruct_f()[jt, it].cpu().numpy()
+    assert np.abs(got - ref).max() <= RTOL * np.abs(ref).max()
+    del g, o
+    torch.cuda.empty_cache()
+    gm = vp.VlasovRun(device="cuda:0", precision="mixed",
+                      **{k: v for k, v in cfg.params().items()
+                         if k != "precision"})
+    gm.init_conditions(torch.as_tensor(f0, device="cuda:0"))
+    del f0
+    gm.step(steps)
+    fm = gm.reconstruct_f()[jt, it].cpu().numpy().astype(np.float64)
+    l2 = np.linalg.norm(fm - ref) / np.linalg.norm(ref)
+    assert l2 <= 1e-5, l2
+    gm.sync()
+    say("done")
+
+
+def test_zero_distribution_stays_zero(vp, orc):
+    """f0 = 0: no mass, no force; f stays exactly zero and the elements
+    stream freely, as on the oracle."""
+    cfg = W.RunConfig("zero", n=128, s=8, dt=1e-3, steps=30, n_s=10, seed=0)
+    f0 = np.zeros((128, 128))
+    o, g = run_pair(vp, orc, cfg, f0)
+    o.step(30)
+    g.step(30)
+    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    f = g.reconstruct_f().cpu().numpy()
+    assert not np.any(f)
+    assert not np.any(g.density().cpu().numpy())
+    g.sync()
+
+
+@pytest.mark.parametrize("n,s", [(8, 8), (16, 16), (8, 1), (8, 2)])
+def test_tiny_grids_and_single_elements(vp, orc, n, s):
+    """The smallest grid, and one element per axis (its window covers the
+    whole box): assignment, f and elements against the oracle."""
+    cfg = W.RunConfig("tiny", n=n, s=s, dt=2e-3, steps=12, n_s=5, seed=0)
+    rng = np.random.default_rng(n * 31 + s)
+    box = (-1.0, 1.0, -1.0, 1.0)
+    f0 = W.finish(W.halo_sum(n, n, box, rng, 2), box, 1.0)
+    o, g = run_pair(vp, orc, cfg, f0)
+    assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(True))
+    o.step(12)
+    g.step(12)
+    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(True))
+    g.sync()
