@@ -18,7 +18,8 @@ namespace vpk {
 constexpr int MAXR = 128;  // run slots of one server
 
 struct PhaseItem {
-  int slot, begin, arg, pad;
+  int slot, begin, arg;
+  int h;  // half steps since the run's last element reset (list geometry)
 };
 struct PhaseTable {
   int n, total, pad0, pad1;
@@ -82,7 +83,8 @@ __global__ __launch_bounds__(256) void kb_elem(
     const int q = find_run(tab, item);
     const PhaseItem pi = tab->it[q];
     const RunDesc<FT> &R = runs[pi.slot];
-    const KP &p = R.k;
+    KP p = R.k;
+    p.tau = 0.5 * p.dt * pi.h;
     const int arg = pi.arg;
     const long long idx = (long long)(item - pi.begin) * 256 + threadIdx.x;
     if (arg & EA_ZERO) {
@@ -129,7 +131,9 @@ __global__ __launch_bounds__(512) void kb_recon(
     const RunDesc<FT> &R = runs[pi.slot];
     const int local = item - pi.begin;
     const int bx = local % R.k.nbx, gy = local / R.k.nbx;
-    recon_tile<FT, MODE>(R.k, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
+    KP p = R.k;
+    p.tau = 0.5 * p.dt * pi.h;
+    recon_tile<FT, MODE>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
                          R.flags, R.F, R.part, R.fout, nullptr, R.dpart, R.ovf,
                          bx, gy);
   }
@@ -169,7 +173,9 @@ __global__ __launch_bounds__(512) void kb_remap(
     const RunDesc<FT> &R = runs[pi.slot];
     const int local = item - pi.begin;
     const int bx = local % R.k.nbx, gy = local / R.k.nbx;
-    remap_tile<FT, 0>(R.k, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
+    KP p = R.k;
+    p.tau = 0.5 * p.dt * pi.h;
+    remap_tile<FT, 0>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
                       R.flags, R.C, R.F, R.ovf, bx, gy);
   }
 }

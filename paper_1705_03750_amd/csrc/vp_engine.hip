@@ -76,9 +76,9 @@ KP make_kp(const vp_params *p) {
   k.E = k.mx * k.mv;
   k.ox = (p->sx / 2) % 8;
   k.ov = (p->sv / 2) % 8;
-  k.obx = k.ox > 0;
+  k.obx = 1;  // block columns shift with the element drift (group_ox)
   k.obv = k.ov > 0;
-  k.nbx = ((p->nx - 1 - k.ox) >> 3) + k.obx + 1;
+  k.nbx = ((p->nx - 1) >> 3) + 2;  // enough for any offset 0..7
   k.nbv = ((p->nv - 1 - k.ov) >> 3) + k.obv + 1;
   k.ngy = ((p->nv - 1 - k.ov) >> 6) + k.obv + 1;
   k.cap = list_cap(p->sx, p->sv);
@@ -159,6 +159,7 @@ struct vp_ctx {
   int64_t step;
   bool ready;
   int cur = 0;  // which of the two block-count buffers holds the live lists
+  int64_t reset_step = 0;  // step of the elements' last reset
   std::string err;
   std::vector<char> host_tab;  // source of the pivot-table upload
   // profiling: event pairs per kernel kind
@@ -234,8 +235,17 @@ int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
   return VP_OK;
 }
 
+// Time since the elements' last reset at which the block lists are built
+// (the positions after the predictor's half drift when `half`); the
+// reconstruction that uses the lists reads the same value from c->k.
+void set_list_time(vp_ctx *c, bool half) {
+  c->k.tau = ((double)(c->step - c->reset_step) + (half ? 0.5 : 0.0)) *
+             c->p.dt;
+}
+
 // Records and block lists for the current element state (no motion).
 int launch_predict(vp_ctx *c, int drift, int reg) {
+  set_list_time(c, drift != 0);
   return launch_elem(c, 0, drift, 1, reg, c->cur, -1);
 }
 
@@ -362,6 +372,7 @@ int do_remap(vp_ctx *c) {
                   : launch_remap_t<double, 0>(c, nullptr);
   if (rc) return rc;
   if ((rc = fit_spline(c))) return rc;
+  c->reset_step = c->step;
   return launch_reset(c);
 }
 
@@ -382,6 +393,7 @@ int run_steps(vp_ctx *c, int n) {
     if (!remap_due && s + 1 < n) {
       // kick + corrector of this step, predictor of the next, lists into
       // the other count buffer while this one is cleared
+      set_list_time(c, true);
       if ((rc = launch_elem(c, 1, 1, 1, self ? 1 : 0, c->cur ^ 1, c->cur)))
         return rc;
       c->cur ^= 1;
@@ -560,6 +572,7 @@ int vp_init_conditions(vp_ctx *c, const double *f0, int f0_on_device) {
   if ((rc = launch_reset(c))) return rc;
   c->t = 0.0;
   c->step = 0;
+  c->reset_step = 0;
   c->ready = true;
   return VP_OK;
 }
@@ -781,6 +794,7 @@ struct Slot {
   int req = -1;
   int nsteps = 0, done = 0;
   bool need_predict = true;
+  int list_h = 0;  // half steps since reset at which the live lists were built
   size_t off = 0, bytes = 0;
 };
 
@@ -906,12 +920,15 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
     tab[ph].n = 0;
     tab[ph].total = 0;
   }
-  auto add = [&](int ph, int slot, int items, int arg) {
+  // h: half steps since the run's last element reset at which block lists
+  // are built (registration phases) or were built (query phases)
+  auto add = [&](int ph, int slot, int items, int arg, int h = 0) {
     PhaseTable &t = tab[ph];
     if (items <= 0) return;
     t.it[t.n].slot = slot;
     t.it[t.n].begin = t.total;
     t.it[t.n].arg = arg;
+    t.it[t.n].h = h;
     t.n += 1;
     t.total += items;
   };
@@ -926,17 +943,21 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
     const int elz_items = ceil_div(std::max<long long>(k.E, c->L.nb), 256);
     const int tiles = k.nbx * k.ngy;
     const int regb = cur ? EA_REGBUF1 : 0, zb = cur ? EA_ZEROBUF1 : 0;
-    if (sl.need_predict)
-      add(PH_PRED, q, el_items, EA_PRED | EA_DRIFT | EA_REG | regb);
-    add(PH_RECON, q, tiles, cur);
+    const int since = (int)(sl.done - c->reset_step);
+    if (sl.need_predict) {
+      sl.list_h = 2 * since + 1;
+      add(PH_PRED, q, el_items, EA_PRED | EA_DRIFT | EA_REG | regb, sl.list_h);
+    }
+    add(PH_RECON, q, tiles, cur, sl.list_h);
     add(PH_FIELD, q, (k.nx + FIELD_WG - 1) / FIELD_WG, 0);
     const int step_after = sl.done + 1;
     const bool remap_due = c->p.n_s > 0 && step_after % c->p.n_s == 0;
     const bool finish = step_after == sl.nsteps;
     if (!remap_due && !finish) {
+      sl.list_h = 2 * (step_after - (int)c->reset_step) + 1;
       add(PH_KICK, q, elz_items,
           EA_KICK | EA_DRIFT | EA_PRED | EA_REG | (cur ? 0 : EA_REGBUF1) |
-              EA_ZERO | zb);
+              EA_ZERO | zb, sl.list_h);
       c->cur ^= 1;
       sl.need_predict = false;
     } else {
@@ -946,16 +967,19 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
     const int cr = c->cur;
     const int regr = cr ? EA_REGBUF1 : 0, zr = cr ? EA_ZEROBUF1 : 0;
     if (remap_due) {
-      add(PH_RM_PRED, q, el_items, EA_PRED | EA_REG | regr);
-      add(PH_RM_EVAL, q, tiles, cr);
+      const int hr = 2 * (step_after - (int)c->reset_step);
+      add(PH_RM_PRED, q, el_items, EA_PRED | EA_REG | regr, hr);
+      add(PH_RM_EVAL, q, tiles, cr, hr);
       add(PH_FIT_X, q, ceil_div(k.nv, 64), 0);
       add(PH_FIT_V, q, ceil_div(k.nx, 64), 0);
       add(PH_GHOST, q, ceil_div(k.nv + 2, 256), 0);
       add(PH_RESET, q, elz_items, EA_RESET | EA_ZERO | zr);
+      c->reset_step = step_after;
     }
     if (finish) {
-      add(PH_FIN_PRED, q, el_items, EA_PRED | EA_REG | regr);
-      add(PH_FIN_RECON, q, tiles, cr);
+      const int hf = 2 * (step_after - (int)c->reset_step);
+      add(PH_FIN_PRED, q, el_items, EA_PRED | EA_REG | regr, hf);
+      add(PH_FIN_RECON, q, tiles, cr, hf);
       add(PH_FIN_ZERO, q, ceil_div(c->L.nb, 256), EA_ZERO | zr);
       finishing.push_back(q);
     }

@@ -10,13 +10,15 @@
 //             interior starting at (PV, PX).  F's padding is zero (data
 //             outside the box); C carries mirror ghosts one site deep.
 //   state     element state, SoA [12][E] doubles.
-//   rec       per-element query record, AoS [E][16] doubles, rebuilt after
-//             every drift: position, A = T^-1, -A/2, H (xv terms doubled).
-//             One record is 128 B: a wavefront loads a candidate with two
-//             scalar loads, the next one while it evaluates the current.
+//   rec       per-element query record, AoS [E][12] doubles (96 B), rebuilt
+//             after every drift: position, A = T^-1, -H/2 (xv terms doubled).
 //   qm        lattice position Q_m of every element, [E][2] doubles.
 //   cnt, lst  element lists of 8x8-site query blocks: every element whose
-//             validity window can reach a block is listed in that block.
+//             validity window holds a site of a block is listed in that
+//             block.  Blocks of one 64-row group are shifted along x to
+//             follow the drift of the elements since their last reset
+//             (group_ox), so that they stay aligned with the element
+//             lattice and a block meets few windows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,6 +51,7 @@ struct KP {
   double G, dt, h, beta;
   int force_mode;
   double a0, a1, a2;
+  double tau;  // time since the elements' last reset (query-block shift)
 };
 
 __device__ __forceinline__ double site_x(const KP &p, int i) {
@@ -61,6 +64,25 @@ __device__ __forceinline__ double site_v(const KP &p, int j) {
 // boundaries sit o sites after a multiple of 8; a partial block 0 when o > 0)
 __device__ __forceinline__ int blk(int i, int o, int ob) {
   return ((i - o) >> 3) + ob;
+}
+
+// Row group (64 rows, one reconstruction workgroup row) of a block row.
+__device__ __forceinline__ int group_of_brow(const KP &p, int bv) {
+  return p.obv + ((bv - p.obv) >> 3);
+}
+
+// x offset (0..7) of the query blocks of row group gy.  Elements drift by
+// v tau along x since their last reset (when they sat on the lattice, at
+// offset ox); the blocks of a row group move with the drift at the group's
+// central velocity, rounded up, so that an element lattice displaced by a
+// fraction of a site meets two blocks per axis instead of three.  Block bx
+// of the group covers columns [o + 8 (bx - 1), o + 8 bx).  Only the work
+// depends on this choice: lists and queries use the same geometry.
+__device__ __forceinline__ int group_ox(const KP &p, int gy) {
+  const double vc = site_v(p, p.ov + 64 * (gy - p.obv) + 32);
+  double d = vc * p.tau * p.inv_dx;
+  if (!(fabs(d) < 1.0e6)) d = 0.0;
+  return (p.ox + (int)ceil(d)) & 7;
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin; give every XCD a
@@ -166,7 +188,8 @@ __device__ __forceinline__ void elem_kick(const KP &p,
 // Query record and block registration of one element; returns false when
 // the element is non-finite or det T <= 0 (flagged, not registered).
 // Can the validity window |A (P - P_m)| < (dx_m, dv_m) of an element hold a
-// site of query block (bxq, bvq)?  l = A (P - P_m) is linear in P, so over
+// site of the query block whose first site is (i0, j0)?  l = A (P - P_m)
+// is linear in P, so over
 // the rectangle spanned by the block's sites it ranges over centre +- the
 // sum of |coefficient| x half-width in each component; the block is skipped
 // only when one component stays outside the window by more than a margin
@@ -174,8 +197,7 @@ __device__ __forceinline__ void elem_kick(const KP &p,
 // the products A_ij dP_j, which may cancel).
 __device__ __forceinline__ bool block_meets_window(
     const KP &p, double X, double V, double axx, double axv, double avx,
-    double avv, int bxq, int bvq) {
-  const int i0 = p.ox + 8 * (bxq - p.obx), j0 = p.ov + 8 * (bvq - p.obv);
+    double avv, int i0, int j0) {
   const int ia = max(0, i0), ib = min(p.nx - 1, i0 + 7);
   const int ja = max(0, j0), jb = min(p.nv - 1, j0 + 7);
   const double xa = site_x(p, ia), xb = site_x(p, ib);
@@ -240,33 +262,39 @@ __device__ __forceinline__ void elem_record(
   const int ilo = max(0, (int)ceil(xlo)), ihi = min(p.nx - 1, (int)floor(xhi));
   const int jlo = max(0, (int)ceil(vlo)), jhi = min(p.nv - 1, (int)floor(vhi));
   if (ilo > ihi || jlo > jhi) return;
-  const int b0x = blk(ilo, p.ox, p.obx), b1x = blk(ihi, p.ox, p.obx);
   const int b0v = blk(jlo, p.ov, p.obv), b1v = blk(jhi, p.ov, p.obv);
-  if ((long long)(b1x - b0x + 1) * (long long)(b1v - b0v + 1) > SPAN_LIMIT) {
+  // blocks per row of the window's box, whatever the row group's x offset
+  const int wxm = ((ihi - ilo) >> 3) + 2, wv = b1v - b0v + 1;
+  if ((long long)wxm * (long long)wv > SPAN_LIMIT) {
     atomicOr(flags, FLAG_WIDE);
     return;
   }
-  // slot claims are independent: issue them eight at a time and only then
-  // write the ids (one atomic round trip per eight blocks, not per block).
-  // A block of the bounding box is listed only if the window can hold one
-  // of its sites (block_meets_window), so sheared windows do not fill the
-  // lists of the blocks their bounding box merely touches.
-  const int wx = b1x - b0x + 1, nblk = wx * (b1v - b0v + 1);
-  for (int q0 = 0; q0 < nblk; q0 += 8) {
-    int bb[8], slot[8];
+  // slot claims are independent: issue them sixteen at a time and only
+  // then write the ids (one atomic round trip per sixteen blocks).
+  // A block of the box is listed only if the window can hold one of its
+  // sites (block_meets_window), so sheared windows do not fill the lists
+  // of the blocks their bounding box merely touches.
+  constexpr int RB = 16;
+  const int nblk = wxm * wv;
+  for (int q0 = 0; q0 < nblk; q0 += RB) {
+    int bb[RB], slot[RB];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < RB; ++k) {
       const int q = q0 + k;
       bb[k] = -1;
       if (q < nblk) {
-        const int bxq = b0x + q % wx, bvq = b0v + q / wx;
-        if (block_meets_window(p, s.x, s.v, axx, axv, avx, avv, bxq, bvq))
+        const int bvq = b0v + q / wxm;
+        const int o = group_ox(p, group_of_brow(p, bvq));
+        const int bxq = blk(ilo, o, 1) + q % wxm;
+        const int i0 = o + 8 * (bxq - 1), j0 = p.ov + 8 * (bvq - p.obv);
+        if (bxq <= blk(ihi, o, 1) &&
+            block_meets_window(p, s.x, s.v, axx, axv, avx, avv, i0, j0))
           bb[k] = bvq * p.nbx + bxq;
       }
       slot[k] = (bb[k] >= 0) ? atomicAdd(&cnt[bb[k]], 1) : p.cap;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < RB; ++k)
       if (slot[k] < p.cap) lst[(size_t)bb[k] * p.cap + slot[k]] = e;
   }
 }
@@ -831,7 +859,8 @@ __device__ __forceinline__ void recon_tile(
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int bv = 8 * (gy - p.obv) + p.obv + w;
-  const int i = p.ox + 8 * (bx - p.obx) + (lane & 7);
+  const int c0 = group_ox(p, gy) + 8 * (bx - 1);
+  const int i = c0 + (lane & 7);
   const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
   const bool blk_ok = bv >= 0 && bv < p.nbv;
   const bool live = blk_ok && i >= 0 && i < p.nx && j >= 0 && j < p.nv;
@@ -888,7 +917,7 @@ __device__ __forceinline__ void recon_tile(
   }
   if (w == 0 && lane < 8) {
     // column partial of this row group: sequential over the 64 rows
-    const int ic = p.ox + 8 * (bx - p.obx) + lane;
+    const int ic = c0 + lane;
     double s = 0.0;
     for (int k = 0; k < 64; ++k) s += sf[(k >> 3) * 64 + (k & 7) * 8 + lane];
     if (ic >= 0 && ic < p.nx) part[(size_t)gy * p.nx + ic] = s;
@@ -925,7 +954,7 @@ __device__ __forceinline__ void remap_tile(
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int bv = 8 * (gy - p.obv) + p.obv + w;
   if (bv < 0 || bv >= p.nbv) return;
-  const int i = p.ox + 8 * (bx - p.obx) + (lane & 7);
+  const int i = group_ox(p, gy) + 8 * (bx - 1) + (lane & 7);
   const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
   const bool live = i >= 0 && i < p.nx && j >= 0 && j < p.nv;
   const int b = bv * p.nbx + bx;
