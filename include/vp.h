@@ -75,7 +75,8 @@ typedef struct vp_params {
                           nx also a multiple of 4 */
   double x_min, x_max; /* phase-space box */
   double v_min, v_max;
-  int32_t sx, sv;      /* element spacing in sites (dx_m = sx dx) */
+  int32_t sx, sv;      /* element spacing in sites (dx_m = sx dx); at most
+                          2^30 elements (nx/sx)(nv/sv) */
   double G;            /* coupling: a(i) = G (M_tot - M_left(i) - M_left(i-1)) */
   double dt;           /* time step, > 0 */
   int32_t n_s;         /* steps between resamplings, 0 = never */

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void kb_elem(
     if (!kick && !pred) continue;
     ElemState s;
     elem_load(R.st, E, e, s);
-    if (kick) elem_kick(p, R.acc, s);
+    if (kick) elem_kick(p, AccTable{R.acc, p.nx + 8}, s);
     if (pred && drift) elem_drift(p, s);
     if (kick || (pred && drift)) elem_store(R.st, E, e, s);
     if (pred)

@@ -52,7 +52,8 @@ bool params_ok(const vp_params *p) {
          (p->precision == VP_FP64 || p->precision == VP_MIXED) &&
          (p->force_mode == VP_FORCE_SELF ||
           p->force_mode == VP_FORCE_EXTERNAL) &&
-         std::isfinite(p->G) && p->nx <= (1 << 17) && p->nv <= (1 << 17);
+         std::isfinite(p->G) && p->nx <= (1 << 17) && p->nv <= (1 << 17) &&
+         (int64_t)(p->nx / p->sx) * (p->nv / p->sv) <= (1 << 30);
 }
 
 // list capacity per 8x8 block: about twice the element count whose windows
@@ -235,6 +236,26 @@ int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
   return VP_OK;
 }
 
+// Field from the reconstruction's partials + kick + corrector (+ next
+// predictor) in one launch (grids of at most FIELD1_MAX columns).
+int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
+                      int zero_buf) {
+  const KP &k = c->k;
+  ProfScope ps(c, PK_KICK);
+  const long long nbz = c->L.nb;
+  const long long n =
+      std::max<long long>(k.E, std::min<long long>(nbz, 1 << 22));
+  hipLaunchKernelGGL(k_elem_field, dim3(grid_for(n, ELEMF_WG)),
+                     dim3(ELEMF_WG), 0, c->stream, k,
+                     c->at<double>(c->L.part), c->at<double>(c->L.st),
+                     c->at<double>(c->L.rec), c->at<double>(c->L.qm),
+                     c->counts(zero_buf), nbz, c->counts(reg_buf),
+                     c->at<int>(c->L.lst), c->at<int>(c->L.flags), predict,
+                     reg);
+  VP_LAUNCH_CHECK(c, "k_elem_field");
+  return VP_OK;
+}
+
 // Time since the elements' last reset at which the block lists are built
 // (the positions after the predictor's half drift when `half`); the
 // reconstruction that uses the lists reads the same value from c->k.
@@ -383,10 +404,19 @@ int do_remap(vp_ctx *c) {
 int run_steps(vp_ctx *c, int n) {
   int rc;
   const bool self = c->p.force_mode == VP_FORCE_SELF;
+  // small grids: the field is rebuilt inside the element pass
+  const bool fused = self && c->k.nx <= FIELD1_MAX;
   bool predicted = false;
   for (int s = 0; s < n; ++s) {
     if (!predicted && (rc = launch_predict(c, 1, self ? 1 : 0))) return rc;
-    if (self && (rc = recon<MODE_DENSITY>(c, nullptr, nullptr))) return rc;
+    if (self) {
+      rc = fused ? (c->mixed() ? launch_recon<float, MODE_DENSITY>(
+                                     c, nullptr, nullptr, nullptr)
+                               : launch_recon<double, MODE_DENSITY>(
+                                     c, nullptr, nullptr, nullptr))
+                 : recon<MODE_DENSITY>(c, nullptr, nullptr);
+      if (rc) return rc;
+    }
     c->step += 1;
     c->t = (double)c->step * c->p.dt;
     const bool remap_due = c->p.n_s > 0 && c->step % c->p.n_s == 0;
@@ -394,12 +424,15 @@ int run_steps(vp_ctx *c, int n) {
       // kick + corrector of this step, predictor of the next, lists into
       // the other count buffer while this one is cleared
       set_list_time(c, true);
-      if ((rc = launch_elem(c, 1, 1, 1, self ? 1 : 0, c->cur ^ 1, c->cur)))
-        return rc;
+      rc = fused ? launch_elem_field(c, 1, 1, c->cur ^ 1, c->cur)
+                 : launch_elem(c, 1, 1, 1, self ? 1 : 0, c->cur ^ 1, c->cur);
+      if (rc) return rc;
       c->cur ^= 1;
       predicted = true;
     } else {
-      if ((rc = launch_elem(c, 1, 0, 0, 0, c->cur, c->cur))) return rc;
+      rc = fused ? launch_elem_field(c, 0, 0, c->cur, c->cur)
+                 : launch_elem(c, 1, 0, 0, 0, c->cur, c->cur);
+      if (rc) return rc;
       predicted = false;
       if (remap_due && (rc = do_remap(c))) return rc;
     }

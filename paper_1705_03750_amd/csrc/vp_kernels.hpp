@@ -152,8 +152,20 @@ __device__ __forceinline__ void elem_drift(const KP &p, ElemState &s) {
   s.hx2 = fma(p.h, s.hv2, s.hx2);
 }
 
-__device__ __forceinline__ void elem_kick(const KP &p,
-                                          const double *__restrict__ acc,
+// Force tables a, a', a'' on the indices [-4, nx + 3] (array index q = i + 4)
+struct AccTable {
+  const double *acc;
+  int n8;
+  __device__ __forceinline__ void at(int q, double &a, double &da,
+                                     double &d2a) const {
+    a = acc[q];
+    da = acc[n8 + q];
+    d2a = acc[2 * n8 + q];
+  }
+};
+
+template <typename Acc>
+__device__ __forceinline__ void elem_kick(const KP &p, const Acc &acc,
                                           ElemState &s) {
   double a, da, d2a;
   if (p.force_mode == 1) {
@@ -169,11 +181,13 @@ __device__ __forceinline__ void elem_kick(const KP &p,
     const double tm = 0.5 - w, tp = 0.5 + w;
     const double w0 = 0.5 * (tm * tm), w1 = 0.75 - w * w, w2 = 0.5 * (tp * tp);
     const int idx = (int)fi + 4;
-    const int n8 = p.nx + 8;
-    const double *A = acc, *DA = acc + n8, *D2A = acc + 2 * n8;
-    a = fma(w2, A[idx + 1], fma(w1, A[idx], w0 * A[idx - 1]));
-    da = fma(w2, DA[idx + 1], fma(w1, DA[idx], w0 * DA[idx - 1]));
-    d2a = fma(w2, D2A[idx + 1], fma(w1, D2A[idx], w0 * D2A[idx - 1]));
+    double am, dam, d2am, a0, da0, d2a0, ap, dap, d2ap;
+    acc.at(idx - 1, am, dam, d2am);
+    acc.at(idx, a0, da0, d2a0);
+    acc.at(idx + 1, ap, dap, d2ap);
+    a = fma(w2, ap, fma(w1, a0, w0 * am));
+    da = fma(w2, dap, fma(w1, da0, w0 * dam));
+    d2a = fma(w2, d2ap, fma(w1, d2a0, w0 * d2am));
   }
   const double dt = p.dt, kdt = dt * da;
   s.v = fma(dt, a, s.v);
@@ -313,7 +327,7 @@ __global__ __launch_bounds__(256) void k_elem(
   const size_t E = (size_t)p.E;
   ElemState s;
   elem_load(st, E, e, s);
-  if (kick) elem_kick(p, acc, s);
+  if (kick) elem_kick(p, AccTable{acc, p.nx + 8}, s);
   if (predict && drift) elem_drift(p, s);
   if (kick || (predict && drift)) elem_store(st, E, e, s);
   if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
@@ -416,6 +430,14 @@ __device__ __forceinline__ void load_rec(const double *__restrict__ rec,
   for (int k = 0; k < RS; ++k) r.v[k] = q[k];
 }
 
+// First entries of a block's list, one per lane, requested before the
+// count is known (the row has cap >= 16 valid slots; entries beyond the
+// count are stale ids and are never used).
+__device__ __forceinline__ int list_head(const KP &p, const int *L) {
+  const int lane = threadIdx.x & 63;
+  return (lane < min(p.cap, 64)) ? L[lane] : 0;
+}
+
 // Records staged per round in a wavefront's LDS area (QSTAGE * RS doubles).
 constexpr int QSTAGE = 20;
 constexpr int RPIECES = RS / 2;  // 16-byte pieces per record
@@ -426,9 +448,11 @@ constexpr int RPIECES = RS / 2;  // 16-byte pieces per record
 // 16-byte piece per lane, about ten records per load instruction), so the
 // candidates cost one memory round trip per QSTAGE records instead of one
 // each; the candidate loop then reads them as uniform LDS broadcasts.
+// L is the block's list row, id0 its first entries (lane-indexed, loaded by
+// the caller together with the count n).
 __device__ __forceinline__ int query_block(
-    const KP &p, const double *__restrict__ rec, const int *__restrict__ lst,
-    int b, int n, bool scan_all, double xP, double vP, double &dqx,
+    const KP &p, const double *__restrict__ rec, const int *__restrict__ L,
+    int id0, int n, bool scan_all, double xP, double vP, double &dqx,
     double &dqv, double *stage) {
   double bd = __builtin_inf();
   int best = -1;
@@ -436,10 +460,9 @@ __device__ __forceinline__ int query_block(
   dqv = 0.0;
   const int lane = threadIdx.x & 63;
   if (!scan_all) {
-    const int *L = lst + (size_t)b * p.cap;
     for (int c0 = 0; c0 < n; c0 += QSTAGE) {
       const int m = min(QSTAGE, n - c0);
-      const int myid = (lane < m) ? L[c0 + lane] : 0;
+      const int myid = (lane < m) ? (c0 == 0 ? id0 : L[c0 + lane]) : 0;
       // pieces lane and lane + 64 (QSTAGE * RPIECES <= 128): both loads
       // are issued before either is stored
       static_assert(QSTAGE * RPIECES <= 128, "two pieces per lane");
@@ -725,48 +748,61 @@ __global__ __launch_bounds__(FIELD_WG) void k_field(KP p, FieldArgs A) {
   field_chunk(p, A, blockIdx.x, L);
 }
 
-// The same field in one workgroup of 1024 threads for grids of at most
-// FIELD1_MAX columns: no cross-workgroup hand-off, M_left stays in LDS.
-// Identical operations in identical order (column sums in increasing group
-// order, 256-site chunk prefixes, sequential carries).
+// The same field in one workgroup for grids of at most FIELD1_MAX columns:
+// no cross-workgroup hand-off, M_left stays in LDS.  Identical operations
+// in identical order (column sums in increasing group order, 256-site chunk
+// prefixes, sequential carries).
 constexpr int FIELD1_MAX = 2048;
 
-__global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
-  __shared__ double M[FIELD1_MAX];
-  __shared__ double car[FIELD1_MAX / FIELD_WG];
+// M_left of every column into LDS M[0, nx) (NT threads, the whole
+// workgroup); returns M_tot.  `in` holds the row-group partials (ngy > 0)
+// or rho (ngy == 0).
+template <int NT>
+__device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
+                                              int ngy, int in_is_rho,
+                                              double *rho_out, double *M,
+                                              double *car) {
+  constexpr int CPT = FIELD1_MAX / NT;  // columns per thread
   const int nx = p.nx, tid = threadIdx.x;
   const int nch = (nx + FIELD_WG - 1) / FIELD_WG;
-  // column values, two columns per thread, loads 16 groups ahead
   {
-    double xs[2] = {0.0, 0.0};
-    const int i0 = tid, i1 = tid + 1024;
-    if (A.ngy > 0) {
-      for (int g0 = 0; g0 < A.ngy; g0 += 16) {
-        double v0[16], v1[16];
+    double xs[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) xs[c] = 0.0;
+    if (ngy > 0) {
+      // increasing group order; loads 16 groups ahead of the additions
+      for (int g0 = 0; g0 < ngy; g0 += 16) {
+        double v[CPT][16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-          const bool g_ok = g0 + u < A.ngy;
-          v0[u] = (g_ok && i0 < nx) ? A.in[(size_t)(g0 + u) * nx + i0] : 0.0;
-          v1[u] = (g_ok && i1 < nx) ? A.in[(size_t)(g0 + u) * nx + i1] : 0.0;
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) {
+            const int i = tid + c * NT;
+            v[c][u] = (g0 + u < ngy && i < nx)
+                          ? in[(size_t)(g0 + u) * nx + i] : 0.0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-          if (g0 + u < A.ngy) {
-            xs[0] += v0[u];
-            xs[1] += v1[u];
+          if (g0 + u < ngy) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) xs[c] += v[c][u];
           }
         }
       }
     } else {
-      if (i0 < nx) xs[0] = A.in[i0];
-      if (i1 < nx) xs[1] = A.in[i1];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int i = tid + c * NT;
+        if (i < nx) xs[c] = in[i];
+      }
     }
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int i = c ? i1 : i0;
+    for (int c = 0; c < CPT; ++c) {
+      const int i = tid + c * NT;
       if (i < nx) {
-        const double rho = A.in_is_rho ? xs[c] : p.dv * xs[c];
-        if (A.rho_out) A.rho_out[i] = rho;
+        const double rho = in_is_rho ? xs[c] : p.dv * xs[c];
+        if (rho_out) rho_out[i] = rho;
         M[i] = p.dx * rho;
       }
     }
@@ -806,34 +842,90 @@ __global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
     }
   }
   __syncthreads();
-  for (int i = tid; i < nx; i += 1024) {
-    const double m = car[i / FIELD_WG] + M[i];
-    M[i] = m;
-    A.Ml[i] = m;
-  }
+  for (int i = tid; i < nx; i += NT) M[i] = car[i / FIELD_WG] + M[i];
   __syncthreads();
-  const double Mtot = M[nx - 1];
-  const int n8 = nx + 8;
+  return M[nx - 1];
+}
+
+// a, a', a'' at table index q (site i = q - 4) from M_left: the operations
+// of the field kernels' force loop.
+__device__ __forceinline__ void acc_from_mass(const KP &p, const double *M,
+                                              double Mtot, int q, double &a0,
+                                              double &da, double &d2a) {
+  const int nx = p.nx, i = q - 4;
   const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
+  const double am = p.G * ((Mtot - Ml_at(M, nx, Mtot, i - 1)) -
+                           Ml_at(M, nx, Mtot, i - 2));
+  a0 = p.G * ((Mtot - Ml_at(M, nx, Mtot, i)) - Ml_at(M, nx, Mtot, i - 1));
+  const double ap = p.G * ((Mtot - Ml_at(M, nx, Mtot, i + 1)) -
+                           Ml_at(M, nx, Mtot, i));
+  da = (ap - am) / two_dx;
+  d2a = ((ap + am) - 2.0 * a0) / dx2;
+}
+
+struct AccFromMass {
+  const KP &p;
+  const double *M;
+  double Mtot;
+  __device__ __forceinline__ void at(int q, double &a, double &da,
+                                     double &d2a) const {
+    acc_from_mass(p, M, Mtot, q, a, da, d2a);
+  }
+};
+
+__global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
+  __shared__ double M[FIELD1_MAX];
+  __shared__ double car[FIELD1_MAX / FIELD_WG];
+  const int nx = p.nx, tid = threadIdx.x;
+  const double Mtot =
+      mass_to_lds<1024>(p, A.in, A.ngy, A.in_is_rho, A.rho_out, M, car);
+  for (int i = tid; i < nx; i += 1024) A.Ml[i] = M[i];
+  const int n8 = nx + 8;
   for (int q = tid; q < n8; q += 1024) {
-    const int i = q - 4;
-    const double am = p.G * ((Mtot - Ml_at(M, nx, Mtot, i - 1)) -
-                             Ml_at(M, nx, Mtot, i - 2));
-    const double a0 = p.G * ((Mtot - Ml_at(M, nx, Mtot, i)) -
-                             Ml_at(M, nx, Mtot, i - 1));
-    const double ap = p.G * ((Mtot - Ml_at(M, nx, Mtot, i + 1)) -
-                             Ml_at(M, nx, Mtot, i));
-    const double da = (ap - am) / two_dx;
-    const double d2a = ((ap + am) - 2.0 * a0) / dx2;
+    double a0, da, d2a;
+    acc_from_mass(p, M, Mtot, q, a0, da, d2a);
     A.acc[q] = a0;
     A.acc[n8 + q] = da;
     A.acc[2 * n8 + q] = d2a;
+    const int i = q - 4;
     if (A.a_out && i >= 0 && i < nx) {
       A.a_out[i] = a0;
       A.da_out[i] = da;
       A.d2a_out[i] = d2a;
     }
   }
+}
+
+// Field and element pass in one launch (grids of at most FIELD1_MAX
+// columns, self-consistent force): every workgroup rebuilds M_left from
+// the reconstruction's row-group partials in LDS (the partials stay in L2;
+// the same operations as the field kernel, so the force is bit-identical),
+// then kicks its elements with it; the rest is k_elem's pass.  Replaces a
+// launch whose single workgroup would leave the GPU idle.
+constexpr int ELEMF_WG = 512;
+
+__global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
+    KP p, const double *__restrict__ part, double *__restrict__ st,
+    double *__restrict__ rec, double *__restrict__ qm,
+    int *__restrict__ cnt_zero, long long nb_zero,
+    int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
+    int predict, int reg) {
+  __shared__ double M[FIELD1_MAX];
+  __shared__ double car[FIELD1_MAX / FIELD_WG];
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
+  const int e = (int)gid;
+  const size_t E = (size_t)p.E;
+  ElemState s;
+  if (e < p.E) elem_load(st, E, e, s);  // in flight during the field
+  const double Mtot =
+      mass_to_lds<ELEMF_WG>(p, part, p.ngy, 0, nullptr, M, car);
+  if (e >= p.E) return;
+  elem_kick(p, AccFromMass{p, M, Mtot}, s);
+  if (predict) elem_drift(p, s);
+  elem_store(st, E, e, s);
+  if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
 }
 
 // ------------------------------------------------------- reconstruction
@@ -868,12 +960,14 @@ __device__ __forceinline__ void recon_tile(
   int best = -1;
   if (blk_ok) {
     const int b = bv * p.nbx + bx;
+    const int *L = lst + (size_t)b * p.cap;
+    const int id0 = list_head(p, L);
     const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
     const bool scan_all = (n > p.cap) || (flags[0] & FLAG_WIDE);
     if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
     const double xP = site_x(p, i), vP = site_v(p, j);
     double dqx, dqv;
-    best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv,
+    best = query_block(p, rec, L, id0, n, scan_all, xP, vP, dqx, dqv,
                        qstage[w]);
     if (live && best >= 0) {
       const double Qx = qm[2 * (size_t)best] + dqx;
@@ -958,12 +1052,14 @@ __device__ __forceinline__ void remap_tile(
   const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
   const bool live = i >= 0 && i < p.nx && j >= 0 && j < p.nv;
   const int b = bv * p.nbx + bx;
+  const int *L = lst + (size_t)b * p.cap;
+  const int id0 = list_head(p, L);
   const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
   const bool scan_all = (n > p.cap) || (flags[0] & FLAG_WIDE);
   if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
   const double xP = site_x(p, i), vP = site_v(p, j);
   double dqx, dqv;
-  const int best = query_block(p, rec, lst, b, n, scan_all, xP, vP, dqx, dqv,
+  const int best = query_block(p, rec, L, id0, n, scan_all, xP, vP, dqx, dqv,
                                qstage[w]);
   if (!live) return;
   FT val = (FT)0;
