@@ -85,6 +85,12 @@ typedef struct vp_params {
   int32_t force_mode;  /* VP_FORCE_SELF or VP_FORCE_EXTERNAL */
   double ext_a0, ext_a1, ext_a2; /* external force coefficients */
   int32_t precision;   /* VP_FP64 or VP_MIXED */
+  double emap_max;     /* adaptive resampling (end of section 2.3.3): every
+                          emap_every steps, resample when E_map (vp_diag)
+                          exceeds emap_max; <= 0 disables.  Independent of
+                          the fixed cadence n_s.  Not accepted by the
+                          serving loop. */
+  int32_t emap_every;  /* steps between E_map checks, >= 1 when enabled */
 } vp_params;
 
 typedef struct vp_diag {
@@ -98,6 +104,11 @@ typedef struct vp_diag {
   double t;           /* current time */
   int64_t step;       /* steps taken since vp_init_conditions */
   int64_t overflow_blocks; /* query blocks that fell back to a full scan */
+  double emap;        /* E_map (end of section 2.3.3): the largest Lagrangian
+                         distance, in element spacings, between the position
+                         Q predicted at a site by its nearest element and by
+                         one of that element's four lattice neighbours whose
+                         validity window holds the site */
 } vp_diag;
 
 typedef struct vp_ctx vp_ctx;

@@ -53,7 +53,8 @@ class _Params(C.Structure):
                 ("n_s", C.c_int32), ("beta", C.c_double),
                 ("force_mode", C.c_int32),
                 ("ext_a0", C.c_double), ("ext_a1", C.c_double),
-                ("ext_a2", C.c_double)]
+                ("ext_a2", C.c_double),
+                ("emap_max", C.c_double), ("emap_every", C.c_int32)]
 
 
 _lib = None
@@ -82,6 +83,7 @@ def lib():
             ("or_remap_position", [vp, i64, pd, pd]),
             ("or_poisson", [vp, pd, pd, pd, pd]),
             ("or_diagnostics", [vp, pd]),
+            ("or_emap", [vp, pd]),
             ("or_get_elements", [vp, pd]),
             ("or_set_elements", [vp, pd]),
             ("or_get_assignment", [vp, C.c_int, P(i32)]),
@@ -134,7 +136,8 @@ def set_threads(n: int) -> int:
 
 class Oracle:
     """One oracle run.  `params` uses the engine's field names (nx, nv,
-    x_min..v_max, sx, sv, G, dt, n_s, beta, force_mode, ext_a0..ext_a2)."""
+    x_min..v_max, sx, sv, G, dt, n_s, beta, force_mode, ext_a0..ext_a2,
+    emap_max, emap_every)."""
 
     def __init__(self, **p):
         self.p = dict(p)
@@ -151,7 +154,9 @@ class Oracle:
                      p["dt"], int(p.get("n_s", 0)),
                      p.get("beta", BETA_DEFAULT),
                      int(p.get("force_mode", FORCE_SELF)),
-                     ext[0], ext[1], ext[2])
+                     ext[0], ext[1], ext[2],
+                     float(p.get("emap_max", 0.0)),
+                     int(p.get("emap_every", 0)))
         self._p = cp
         h = lib().or_create(C.byref(cp))
         if not h:
@@ -222,6 +227,12 @@ class Oracle:
         keys = ("mass", "e_kin", "e_pot", "energy", "entropy", "max_det_dev",
                 "t")
         return dict(zip(keys, out.tolist()))
+
+    def emap(self) -> float:
+        """E_map of the current elements, in element-spacing units."""
+        out = C.c_double(0.0)
+        _check(lib().or_emap(self.h, C.byref(out)), "emap")
+        return out.value
 
     def get_elements(self) -> np.ndarray:
         out = np.empty((12, self.E))

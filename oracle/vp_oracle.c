@@ -462,6 +462,48 @@ static double remap_site(const or_ctx *c, int i, int j) {
   return or_spline_eval(c->C, c->nx, c->nv, sx, sv);
 }
 
+/* Mismatch of the Lagrangian positions predicted at site P by the nearest
+ * element and by each of its lattice neighbours (section 2.3.3, end): the
+ * Lagrangian distance of eq. (distdef) between the two predictions, in
+ * element-spacing units.  Reading R21: the neighbours are the four lattice
+ * neighbours (k +- 1, l), (k, l +- 1) of the nearest element that exist and
+ * whose validity window holds P (reading R8), and the site value is the
+ * largest mismatch over them (0 when none). */
+static double emap_site(const or_ctx *c, double xP, double vP) {
+  double dqx = 0.0, dqv = 0.0;
+  int e = query_bucketed(c, xP, vP, &dqx, &dqv);
+  if (e < 0) return 0.0;
+  int k0 = e % c->mx, l0 = e / c->mx;
+  double qx0 = elem_qx(c, k0) + dqx, qv0 = elem_qv(c, l0) + dqv;
+  static const int nk[4] = {-1, 1, 0, 0}, nl[4] = {0, 0, -1, 1};
+  double worst = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    int k = k0 + nk[q], l = l0 + nl[q];
+    if (k < 0 || k >= c->mx || l < 0 || l >= c->mv) continue;
+    double ex, ev;
+    if (!elem_map(c, l * c->mx + k, xP, vP, &ex, &ev)) continue;
+    double mx = (elem_qx(c, k) + ex) - qx0;
+    double mv = (elem_qv(c, l) + ev) - qv0;
+    double d = sqrt(dist2(c, mx, mv));
+    if (d > worst) worst = d;
+  }
+  return worst;
+}
+
+/* E_map: the largest neighbour mismatch over all sites, for the current
+ * element state (positions at the current time, no drift). */
+static double emap_all(const or_ctx *c) {
+  int nx = c->nx, nv = c->nv;
+  double worst = 0.0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(max : worst)
+  for (int j = 0; j < nv; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double d = emap_site(c, site_x(c, i), site_v(c, j));
+      if (d > worst) worst = d;
+    }
+  return worst;
+}
+
 static void reconstruct_all(or_ctx *c, double *f, int brute, int32_t *assign) {
   int nx = c->nx, nv = c->nv;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -730,11 +772,28 @@ int or_step(or_ctx *c, int nsteps) {
     kick_and_correct(c);
     c->step += 1;
     c->t = (double)c->step * c->p.dt;
-    if (c->p.n_s > 0 && c->step % c->p.n_s == 0) {
+    int remap = c->p.n_s > 0 && c->step % c->p.n_s == 0;
+    if (!remap && c->p.emap_max > 0.0 && c->p.emap_every > 0 &&
+        c->step % c->p.emap_every == 0) {
+      /* adaptive resampling (section 2.3.3, end): remap when the neighbour
+       * mismatch of the current elements exceeds the threshold */
+      rc = prepare_query(c);
+      if (rc) return rc;
+      remap = emap_all(c) > c->p.emap_max;
+    }
+    if (remap) {
       rc = or_remap(c);
       if (rc) return rc;
     }
   }
+  return OR_OK;
+}
+
+int or_emap(or_ctx *c, double *emap) {
+  if (!c || !c->ready || !emap) return OR_ESTATE;
+  int rc = prepare_query(c);
+  if (rc) return rc;
+  *emap = emap_all(c);
   return OR_OK;
 }
 

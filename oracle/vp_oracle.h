@@ -45,6 +45,8 @@ typedef struct or_params {
   double beta;
   int32_t force_mode;
   double ext_a0, ext_a1, ext_a2;
+  double emap_max;     /* adaptive remap threshold on E_map (<= 0: off) */
+  int32_t emap_every;  /* steps between E_map checks (adaptive remap) */
 } or_params;
 
 typedef struct or_ctx or_ctx;
@@ -62,6 +64,7 @@ int or_density(or_ctx *c, double *rho_out);
 int or_poisson(or_ctx *c, const double *rho, double *a, double *da,
                double *d2a);
 int or_diagnostics(or_ctx *c, double *out7);
+int or_emap(or_ctx *c, double *emap);
 int or_get_elements(or_ctx *c, double *out);
 int or_set_elements(or_ctx *c, const double *in);
 int or_get_assignment(or_ctx *c, int brute, int32_t *out);

@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("n_s", C.c_int32), ("beta", C.c_double),
                 ("force_mode", C.c_int32),
                 ("ext_a0", C.c_double), ("ext_a1", C.c_double),
-                ("ext_a2", C.c_double), ("precision", C.c_int32)]
+                ("ext_a2", C.c_double), ("precision", C.c_int32),
+                ("emap_max", C.c_double), ("emap_every", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -52,7 +53,7 @@ class Diag(C.Structure):
                 ("e_pot", C.c_double), ("energy", C.c_double),
                 ("entropy", C.c_double), ("max_det_dev", C.c_double),
                 ("t", C.c_double), ("step", C.c_int64),
-                ("overflow_blocks", C.c_int64)]
+                ("overflow_blocks", C.c_int64), ("emap", C.c_double)]
 
 
 class Request(C.Structure):
@@ -135,7 +136,7 @@ def lib():
 def make_params(nx, nv=None, x_min=-1.0, x_max=1.0, v_min=-1.0, v_max=1.0,
                 sx=8, sv=None, G=1.0, dt=1e-3, n_s=0, beta=BETA_PAPER,
                 force_mode=FORCE_SELF, ext=(0.0, 0.0, 0.0),
-                precision="fp64") -> Params:
+                precision="fp64", emap_max=0.0, emap_every=0) -> Params:
     prec = {"fp64": FP64, "mixed": MIXED}[precision] \
         if isinstance(precision, str) else int(precision)
     nv = nx if nv is None else nv
@@ -143,7 +144,8 @@ def make_params(nx, nv=None, x_min=-1.0, x_max=1.0, v_min=-1.0, v_max=1.0,
     return Params(int(nx), int(nv), float(x_min), float(x_max), float(v_min),
                   float(v_max), int(sx), int(sv), float(G), float(dt),
                   int(n_s), float(beta), int(force_mode), float(ext[0]),
-                  float(ext[1]), float(ext[2]), prec)
+                  float(ext[1]), float(ext[2]), prec, float(emap_max),
+                  int(emap_every))
 
 
 def footprint(**kw) -> int:
@@ -159,7 +161,8 @@ class VlasovRun:
     """One run of the engine on a CUDA (HIP) device.
 
     Keyword parameters follow vp_params (nx, nv, x_min..v_max, sx, sv, G,
-    dt, n_s, beta, force_mode, ext=(a0, a1, a2), precision='fp64'|'mixed').
+    dt, n_s, beta, force_mode, ext=(a0, a1, a2), precision='fp64'|'mixed',
+    emap_max, emap_every).
     The workspace is one torch uint8 tensor; work is enqueued on the current
     torch stream of `device` (or `stream`, a torch.cuda.Stream)."""
 

@@ -53,7 +53,8 @@ bool params_ok(const vp_params *p) {
          (p->force_mode == VP_FORCE_SELF ||
           p->force_mode == VP_FORCE_EXTERNAL) &&
          std::isfinite(p->G) && p->nx <= (1 << 17) && p->nv <= (1 << 17) &&
-         (int64_t)(p->nx / p->sx) * (p->nv / p->sv) <= (1 << 30);
+         (int64_t)(p->nx / p->sx) * (p->nv / p->sv) <= (1 << 30) &&
+         !(p->emap_max > 0.0 && p->emap_every < 1) && !std::isnan(p->emap_max);
 }
 
 // list capacity per 8x8 block: about twice the element count whose windows
@@ -136,7 +137,7 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.ctot = take((size_t)FIELD_CHUNKS * 8);
   L.Ml = take((size_t)k.nx * 8);
   L.acc = take((size_t)3 * (k.nx + 8) * 8);
-  L.dpart = take((size_t)2 * k.nbx * k.ngy * 8);
+  L.dpart = take((size_t)3 * k.nbx * k.ngy * 8);
   L.dout = take(16 * 8);
   L.tab = take((size_t)2 * (k.nx + k.nv) * fb);
   L.total = o;
@@ -397,6 +398,30 @@ int do_remap(vp_ctx *c) {
   return launch_reset(c);
 }
 
+// Diagnostics of the current state (positions at the current time): mass,
+// kinetic and potential energy, entropy, max |det T - 1|, E_map into h[6],
+// and the count of overflowed query blocks.  Synchronises the stream.
+int diag_now(vp_ctx *c, double *h, unsigned long long *ovf) {
+  int rc;
+  if ((rc = launch_predict(c, 0, 1))) return rc;
+  if ((rc = recon<MODE_DIAG>(c, nullptr, nullptr))) return rc;
+  if ((rc = launch_zero_counts(c))) return rc;
+  hipLaunchKernelGGL(k_diag, dim3(1), dim3(1024), 0, c->stream, c->k,
+                     c->at<double>(c->L.dpart),
+                     (long long)c->L.nwg_x * c->L.nwg_y,
+                     c->at<double>(c->L.Ml), c->at<double>(c->L.acc),
+                     c->at<double>(c->L.st), c->at<double>(c->L.dout));
+  VP_LAUNCH_CHECK(c, "k_diag");
+  hipError_t e = hipMemcpyAsync(h, c->at<double>(c->L.dout), 6 * sizeof(double),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ovf, c->at<unsigned long long>(c->L.ovf), sizeof(*ovf),
+                       hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "diagnostics read");
+  return VP_OK;
+}
+
 // n drift-kick-drift steps.  The kick + corrector of a step and the
 // predictor of the next one share one element pass (k_elem) unless a
 // resampling or the end of the call comes between them, so the elements are
@@ -420,7 +445,11 @@ int run_steps(vp_ctx *c, int n) {
     c->step += 1;
     c->t = (double)c->step * c->p.dt;
     const bool remap_due = c->p.n_s > 0 && c->step % c->p.n_s == 0;
-    if (!remap_due && s + 1 < n) {
+    // adaptive resampling: E_map of the post-corrector elements is checked
+    // every emap_every steps (end of section 2.3.3)
+    const bool check_due = !remap_due && c->p.emap_max > 0.0 &&
+                           c->step % c->p.emap_every == 0;
+    if (!remap_due && !check_due && s + 1 < n) {
       // kick + corrector of this step, predictor of the next, lists into
       // the other count buffer while this one is cleared
       set_list_time(c, true);
@@ -434,7 +463,14 @@ int run_steps(vp_ctx *c, int n) {
                  : launch_elem(c, 1, 0, 0, 0, c->cur, c->cur);
       if (rc) return rc;
       predicted = false;
-      if (remap_due && (rc = do_remap(c))) return rc;
+      bool remap = remap_due;
+      if (check_due) {
+        double h[6];
+        unsigned long long ovf = 0;
+        if ((rc = diag_now(c, h, &ovf))) return rc;
+        remap = h[5] > c->p.emap_max;
+      }
+      if (remap && (rc = do_remap(c))) return rc;
     }
   }
   return VP_OK;
@@ -658,31 +694,17 @@ int vp_poisson(vp_ctx *c, const double *rho, double *a, double *da,
 int vp_diagnostics(vp_ctx *c, vp_diag *out) {
   if (!c || !out) return VP_EINVAL;
   if (!c->ready) return VP_ESTATE;
-  int rc;
-  if ((rc = launch_predict(c, 0, 1))) return rc;
-  if ((rc = recon<MODE_DIAG>(c, nullptr, nullptr))) return rc;
-  if ((rc = launch_zero_counts(c))) return rc;
-  hipLaunchKernelGGL(k_diag, dim3(1), dim3(1024), 0, c->stream, c->k,
-                     c->at<double>(c->L.dpart),
-                     (long long)c->L.nwg_x * c->L.nwg_y,
-                     c->at<double>(c->L.Ml), c->at<double>(c->L.acc),
-                     c->at<double>(c->L.st), c->at<double>(c->L.dout));
-  VP_LAUNCH_CHECK(c, "k_diag");
-  double h[8];
+  double h[6];
   unsigned long long ovf = 0;
-  hipError_t e = hipMemcpyAsync(h, c->at<double>(c->L.dout), 5 * sizeof(double),
-                                hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&ovf, c->at<unsigned long long>(c->L.ovf), sizeof(ovf),
-                       hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return dev_fail(c, e, "diagnostics read");
+  int rc = diag_now(c, h, &ovf);
+  if (rc) return rc;
   out->mass = h[0];
   out->e_kin = h[1];
   out->e_pot = h[2];
   out->energy = h[1] + h[2];
   out->entropy = h[3];
   out->max_det_dev = h[4];
+  out->emap = h[5];
   out->t = c->t;
   out->step = c->step;
   out->overflow_blocks = (int64_t)ovf;
@@ -1196,7 +1218,7 @@ int vp_server_run(vp_server *s, const vp_request *reqs, int n,
       size_t need = 0;
       int q = -1;
       if (rq.params.precision != s->precision || rq.nsteps < 1 ||
-          !rq.f0_dev || !rq.f_out_dev ||
+          !rq.f0_dev || !rq.f_out_dev || rq.params.emap_max > 0.0 ||
           vp_footprint(&rq.params, &need) != VP_OK ||
           align_up(need) > s->pool_bytes - header_bytes(s->precision)) {
         res[r].status = VP_EINVAL;

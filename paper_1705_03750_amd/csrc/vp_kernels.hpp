@@ -418,6 +418,18 @@ __device__ __forceinline__ void element_map(const KP &p,
   dqv = fma(r[R_AVX], ux, fma(r[R_AVV], uv, lv));
 }
 
+// The map with its validity (the neighbour predictions of E_map).
+__device__ __forceinline__ bool element_map_valid(const KP &p,
+                                                  const double *__restrict__ r,
+                                                  double xP, double vP,
+                                                  double &dqx, double &dqv) {
+  const double dx = xP - r[R_X], dv = vP - r[R_V];
+  const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
+  const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
+  element_map(p, r, xP, vP, dqx, dqv);
+  return fabs(lx) < p.dxm && fabs(lv) < p.dvm;
+}
+
 struct Rec {
   double v[RS];
   __device__ __forceinline__ double operator[](int k) const { return v[k]; }
@@ -956,7 +968,7 @@ __device__ __forceinline__ void recon_tile(
   const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
   const bool blk_ok = bv >= 0 && bv < p.nbv;
   const bool live = blk_ok && i >= 0 && i < p.nx && j >= 0 && j < p.nv;
-  double f = 0.0;
+  double f = 0.0, em = 0.0;
   int best = -1;
   if (blk_ok) {
     const int b = bv * p.nbx + bx;
@@ -982,6 +994,26 @@ __device__ __forceinline__ void recon_tile(
       fout[(size_t)j * p.nx + i] = (FT)0;
     }
     if (MODE == MODE_ASSIGN && live) aout[(size_t)j * p.nx + i] = best;
+    if (MODE == MODE_DIAG && live && best >= 0) {
+      // E_map at this site: distance between the nearest element's
+      // prediction of Q and those of its valid lattice neighbours
+      const int l0 = best / p.mx, k0 = best - l0 * p.mx;
+      const double qx0 = qm[2 * (size_t)best] + dqx;
+      const double qv0 = qm[2 * (size_t)best + 1] + dqv;
+      const int nk[4] = {-1, 1, 0, 0}, nl[4] = {0, 0, -1, 1};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + nk[q], l = l0 + nl[q];
+        if (k < 0 || k >= p.mx || l < 0 || l >= p.mv) continue;
+        const size_t m = (size_t)l * p.mx + k;
+        double ex, ev;
+        if (!element_map_valid(p, rec + m * RS, xP, vP, ex, ev)) continue;
+        const double mx = (qm[2 * m] + ex) - qx0;
+        const double mv = (qm[2 * m + 1] + ev) - qv0;
+        const double zx = mx * p.rx, zv = mv * p.rv;
+        em = fmax(em, sqrt(fma(zx, zx, zv * zv)));
+      }
+    }
   }
   if (MODE != MODE_DENSITY && MODE != MODE_DIAG) return;
   if (!live) f = 0.0;
@@ -992,21 +1024,25 @@ __device__ __forceinline__ void recon_tile(
   }
   __syncthreads();
   if (MODE == MODE_DIAG) {
-    // fixed-order tree sums of v^2 f and f ln|f| over the workgroup
-    __shared__ double se[512];
+    // fixed-order tree sums of v^2 f and f ln|f|, and the largest E_map
+    // site value, over the workgroup
+    __shared__ double se[512], sm[512];
     se[threadIdx.x] = (f != 0.0) ? f * log(fabs(f)) : 0.0;
+    sm[threadIdx.x] = em;
     __syncthreads();
     for (int s = 256; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
         sk[threadIdx.x] += sk[threadIdx.x + s];
         se[threadIdx.x] += se[threadIdx.x + s];
+        sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
       }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
       const size_t wg = (size_t)gy * p.nbx + bx;
-      dpart[2 * wg] = sk[0];
-      dpart[2 * wg + 1] = se[0];
+      dpart[3 * wg] = sk[0];
+      dpart[3 * wg + 1] = se[0];
+      dpart[3 * wg + 2] = sm[0];
     }
   }
   if (w == 0 && lane < 8) {
@@ -1126,12 +1162,13 @@ __global__ __launch_bounds__(1024) void k_diag(
     KP p, const double *__restrict__ dpart, long long nwg,
     const double *__restrict__ Ml, const double *__restrict__ acc,
     const double *__restrict__ st, double *__restrict__ out) {
-  __shared__ double s0[1024], s1[1024], s2[1024], s3[1024];
+  __shared__ double s0[1024], s1[1024], s2[1024], s3[1024], s4[1024];
   const int tid = threadIdx.x;
-  double kin = 0.0, ent = 0.0, pot = 0.0, mdet = 0.0;
+  double kin = 0.0, ent = 0.0, pot = 0.0, mdet = 0.0, emap = 0.0;
   for (long long q = tid; q < nwg; q += blockDim.x) {
-    kin += dpart[2 * q];
-    ent += dpart[2 * q + 1];
+    kin += dpart[3 * q];
+    ent += dpart[3 * q + 1];
+    emap = fmax(emap, dpart[3 * q + 2]);
   }
   const double Mtot = Ml[p.nx - 1];
   const int n8 = p.nx + 8;
@@ -1162,6 +1199,7 @@ __global__ __launch_bounds__(1024) void k_diag(
   s1[tid] = ent;
   s2[tid] = pot;
   s3[tid] = mdet;
+  s4[tid] = emap;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
     if (tid < s) {
@@ -1169,6 +1207,7 @@ __global__ __launch_bounds__(1024) void k_diag(
       s1[tid] += s1[tid + s];
       s2[tid] += s2[tid + s];
       s3[tid] = fmax(s3[tid], s3[tid + s]);
+      s4[tid] = fmax(s4[tid], s4[tid + s]);
     }
     __syncthreads();
   }
@@ -1182,6 +1221,7 @@ __global__ __launch_bounds__(1024) void k_diag(
       out[2] = s2[0];
     out[3] = -s1[0] * cell;
     out[4] = s3[0];
+    out[5] = s4[0];
   }
 }
 

@@ -666,3 +666,73 @@ def test_paper_printed_values(orc):
     o2 = orc.Oracle(**box_params(n, 4))
     o2.init_conditions(fg)
     assert abs(o2.diagnostics()["mass"] - gs["total_mass"]) < 0.01
+
+
+# ------------------------------------------ E_map (end of section 2.3.3)
+def _anharmonic_run(orc, s, n=256, steps=15, **kw):
+    box = (-1, 1, -1, 1)
+    f0 = W.finish(W.gaussian_blob(n, n, box, 0.05, 0.1, 0.15, 0.15), box,
+                  mass=None)
+    o = orc.Oracle(**box_params(n, s, dt=0.02, force_mode=orc.FORCE_EXTERNAL,
+                                ext=(0.1, -1.3, 2.1), **kw))
+    o.init_conditions(f0)
+    o.step(steps)
+    return o
+
+
+def test_emap_is_zero_on_a_fresh_lattice(orc):
+    """At a reset every element predicts Q = P exactly (T = I, H = 0, and
+    P - Q_m is exact on the dyadic grid), so neighbouring predictions
+    coincide."""
+    cfg, f0 = W.config("c1_gaussian_256", n=64)
+    o = orc.Oracle(**box_params(64, 4))
+    o.init_conditions(f0)
+    assert o.emap() == 0.0
+
+
+@pytest.mark.parametrize("mode", ["free", "harmonic"])
+def test_emap_vanishes_for_linear_flows(orc, mode):
+    """A force linear in x makes the map linear: H stays zero, every
+    element's expansion is exact, and all predictions of Q agree to
+    rounding."""
+    box = (-1, 1, -1, 1)
+    kw = (dict(G=0.0) if mode == "free" else
+          dict(force_mode=orc.FORCE_EXTERNAL, ext=(0.0, -2.0, 0.0)))
+    o = orc.Oracle(**box_params(64, 4, dt=0.01, **kw))
+    o.init_conditions(W.finish(W.gaussian_blob(64, 64, box, 0, 0, 0.2, 0.2),
+                               box, mass=None))
+    o.step(25)
+    assert not np.any(o.get_elements()[6:])
+    assert o.emap() < 1e-12
+
+
+def test_emap_is_third_order_in_the_element_spacing(orc):
+    """Under an anharmonic force neighbouring second-order predictions
+    differ by the third-order remainder of the map: halving the element
+    spacing on the same grid and flow divides the absolute mismatch
+    (E_map x element spacing) by 8."""
+    absolute = []
+    for s in (16, 8, 4):
+        o = _anharmonic_run(orc, s)
+        absolute.append(o.emap() * s * (2.0 / 256))
+    for a, b in zip(absolute, absolute[1:]):
+        assert 2.8 < math.log2(a / b) < 3.2, absolute
+
+
+def test_adaptive_remap_follows_the_threshold(orc):
+    """With adaptive resampling, a check after step 5 remaps (fresh T = I)
+    exactly when E_map of that state exceeds the threshold."""
+    ref = _anharmonic_run(orc, 8, n=128, steps=5)
+    e5 = ref.emap()
+    assert e5 > 0.0
+    for thr, expect_remap in ((0.5 * e5, True), (2.0 * e5, False)):
+        o = _anharmonic_run(orc, 8, n=128, steps=5, emap_max=thr,
+                            emap_every=5)
+        el = o.get_elements()
+        fresh = np.all(el[2] == 1.0) and np.all(el[5] == 1.0) and \
+            not np.any(el[3]) and not np.any(el[4])
+        assert fresh == expect_remap, (thr, e5)
+    # checks at other steps only
+    o = _anharmonic_run(orc, 8, n=128, steps=5, emap_max=0.5 * e5,
+                        emap_every=3)
+    assert not np.all(o.get_elements()[2] == 1.0)
