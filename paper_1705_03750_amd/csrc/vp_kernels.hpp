@@ -199,16 +199,13 @@ __device__ __forceinline__ void elem_kick(const KP &p, const Acc &acc,
   elem_drift(p, s);
 }
 
-// Query record and block registration of one element; returns false when
-// the element is non-finite or det T <= 0 (flagged, not registered).
 // Can the validity window |A (P - P_m)| < (dx_m, dv_m) of an element hold a
-// site of the query block whose first site is (i0, j0)?  l = A (P - P_m)
-// is linear in P, so over
-// the rectangle spanned by the block's sites it ranges over centre +- the
-// sum of |coefficient| x half-width in each component; the block is skipped
-// only when one component stays outside the window by more than a margin
-// that covers the rounding of l at the sites (relative to the magnitudes of
-// the products A_ij dP_j, which may cancel).
+// site of the query block whose first site is (i0, j0)?  l = A (P - P_m) is
+// linear in P, so over the rectangle spanned by the block's sites it ranges
+// over centre +- the sum of |coefficient| x half-width in each component;
+// the block is skipped only when one component stays outside the window by
+// more than a margin that covers the rounding of l at the sites (relative
+// to the magnitudes of the products A_ij dP_j, which may cancel).
 __device__ __forceinline__ bool block_meets_window(
     const KP &p, double X, double V, double axx, double axv, double avx,
     double avv, int i0, int j0) {
@@ -228,6 +225,8 @@ __device__ __forceinline__ bool block_meets_window(
   return fabs(lxc) - rx < p.dxm + tx && fabs(lvc) - rv < p.dvm + tv;
 }
 
+// Query record and block registration of one element.  A non-finite
+// element or det T <= 0 raises FLAG_NUMERIC and is not registered.
 __device__ __forceinline__ void elem_record(
     const KP &p, const ElemState &s, int e, double *__restrict__ rec,
     double *__restrict__ qm, int *__restrict__ cnt, int *__restrict__ lst,
