@@ -519,8 +519,10 @@ static void reconstruct_all(or_ctx *c, double *f, int brute, int32_t *assign) {
 
 /* Column sums S(i) = sum_j f(i, j) in a fixed order (reading C9): rows are
  * taken in groups of 64, the group boundaries falling on rows congruent to
- * o = (sv/2 mod 8) modulo 64; each group is summed sequentially in j and the
- * group partials are added sequentially in increasing group order. */
+ * o = (sv/2 mod 8) modulo 64, each group made of 8-row strips with
+ * boundaries on rows congruent to o modulo 8; a strip is summed
+ * sequentially in j, a group adds its strips in order, and the group
+ * partials are added sequentially in increasing group order. */
 static void column_sums(const or_ctx *c, const double *f, double *S) {
   int nx = c->nx, nv = c->nv, o = (c->p.sv / 2) % 8;
   for (int i = 0; i < nx; ++i) S[i] = 0.0;
@@ -531,7 +533,17 @@ static void column_sums(const or_ctx *c, const double *f, double *S) {
     if (jend > nv) jend = nv;
     for (int i = 0; i < nx; ++i) {
       double part = 0.0;
-      for (int jj = j; jj < jend; ++jj) part += f[(size_t)jj * nx + i];
+      int js = j;
+      while (js < jend) {
+        /* an 8-row strip: rows up to the next row = o (mod 8) */
+        int s8 = (int)floor((double)(js - o) / 8.0);
+        int jse = o + 8 * (s8 + 1);
+        if (jse > jend) jse = jend;
+        double strip = 0.0;
+        for (int jj = js; jj < jse; ++jj) strip += f[(size_t)jj * nx + i];
+        part += strip;
+        js = jse;
+      }
       S[i] += part;
     }
     j = jend;

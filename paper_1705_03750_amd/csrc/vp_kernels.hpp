@@ -944,10 +944,11 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
 // One workgroup = 8 wavefronts stacked in v; one wavefront = one 8x8-site
 // query block (lane -> site: x = lane & 7, v = lane >> 3).  The workgroup
 // covers 8 columns x 64 rows, the row group of the fixed column-sum order.
-// In the density modes each workgroup writes the 8 column partials of its
-// row group (sequential over the 64 rows); the field kernel adds them in
-// increasing group order.  No workgroup waits on another, so the launch
-// needs no device-scope synchronisation.
+// In the density modes each wavefront sums its 8-row strip per column
+// (sequential over the rows), and each workgroup writes the 8 column
+// partials of its row group (the strips in order); the field adds the
+// groups in increasing order.  No workgroup waits on another, so the
+// launch needs no device-scope synchronisation.
 template <typename FT, int MODE>
 __device__ __forceinline__ void recon_tile(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
@@ -1021,6 +1022,18 @@ __device__ __forceinline__ void recon_tile(
     const double vj = live ? site_v(p, j) : 0.0;
     sk[threadIdx.x] = vj * vj * f;
   }
+  // column partial of this wavefront's 8-row strip, sequential over the rows
+  __shared__ double sp[64];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane < 8) {
+    const double *col = sf + w * 64 + lane;
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s += col[r * 8];
+    sp[w * 8 + lane] = s;
+  }
   __syncthreads();
   if (MODE == MODE_DIAG) {
     // fixed-order tree sums of v^2 f and f ln|f|, and the largest E_map
@@ -1045,10 +1058,11 @@ __device__ __forceinline__ void recon_tile(
     }
   }
   if (w == 0 && lane < 8) {
-    // column partial of this row group: sequential over the 64 rows
+    // column partial of this row group: the eight strip partials in order
     const int ic = c0 + lane;
     double s = 0.0;
-    for (int k = 0; k < 64; ++k) s += sf[(k >> 3) * 64 + (k & 7) * 8 + lane];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += sp[k * 8 + lane];
     if (ic >= 0 && ic < p.nx) part[(size_t)gy * p.nx + ic] = s;
   }
 }
