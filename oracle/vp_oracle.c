@@ -551,13 +551,13 @@ static void column_sums(const or_ctx *c, const double *f, double *S) {
 }
 
 /* Cumulative mass M_left(i) = sum_{m <= i} M(m) of section 2.5, taken in
- * chunks of 256 sites: sequential inside a chunk, the chunk carries added
+ *  chunks of 64 sites: sequential inside a chunk, the chunk carries added
  * sequentially (reading C9).  M_tot is the last cumulative value (R13). */
 static void cumulative_mass(or_ctx *c, const double *M) {
   int n = c->nx;
   double carry = 0.0;
-  for (int c0 = 0; c0 < n; c0 += 256) {
-    int c1 = c0 + 256 < n ? c0 + 256 : n;
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    int c1 = c0 + 64 < n ? c0 + 64 : n;
     double p = 0.0;
     for (int i = c0; i < c1; ++i) {
       p += M[i];

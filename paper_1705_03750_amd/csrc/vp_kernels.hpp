@@ -607,13 +607,13 @@ __device__ __forceinline__ double W_kernel(double x) {
 // ------------------------------------------------------------- the field
 
 // Cumulative mass and force (section 2.5, eq. acccomp; a' as a centred
-// difference over 2 dx).  M_left is summed in 256-site chunks, sequentially
+// difference over 2 dx).  M_left is summed in 64-site chunks, sequentially
 // inside a chunk, and the chunk carries are added sequentially.  One
-// workgroup of 256 threads handles one chunk: it forms the column values
+// workgroup of 256 threads handles 256 columns: it forms the column values
 // (sum of the row-group partials in increasing group order, or rho given
-// directly), the chunk's sequential prefix and its total; the last chunk
-// workgroup to finish adds the carries and writes M_left and a, a', a''
-// on the indices [-4, nx + 3] (plus optional copies on [0, nx)).
+// directly), the sequential prefix and total of each of its chunks; the
+// last workgroup to finish adds the carries and writes M_left and a, a',
+// a'' on the indices [-4, nx + 3] (plus optional copies on [0, nx)).
 __device__ __forceinline__ double Ml_at(const double *Ml, int nx, double Mtot,
                                         int i) {
   if (i < 0) return 0.0;
@@ -621,8 +621,33 @@ __device__ __forceinline__ double Ml_at(const double *Ml, int nx, double Mtot,
   return Ml[i];
 }
 
-constexpr int FIELD_CHUNKS = 1024;  // up to 262144 columns
-constexpr int FIELD_WG = 256;
+constexpr int MCHUNK = 64;          // cumulative-mass chunk (sites)
+constexpr int FIELD_CHUNKS = 2048;  // chunks: up to 131072 columns
+constexpr int FIELD_WG = 256;       // columns per workgroup of k_field
+
+// Sequential running sum of st[0, n) in place; returns the total.  Loads
+// are batched ahead of the dependency chain.
+__device__ __forceinline__ double seq_prefix(double *st, int n) {
+  double s = 0.0;
+  const int nb = n & ~15;
+  for (int q0 = 0; q0 < nb; q0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = st[q0 + u];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      s += v[u];
+      v[u] = s;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) st[q0 + u] = v[u];
+  }
+  for (int q = nb; q < n; ++q) {
+    s += st[q];
+    st[q] = s;
+  }
+  return s;
+}
 
 struct FieldArgs {
   const double *in;   // row-group partials [ngy][nx] or rho [nx]
@@ -652,7 +677,8 @@ struct FieldLds {
 __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
                                             int c, FieldLds &L) {
   const int nx = p.nx, tid = threadIdx.x;
-  const int nch = (nx + FIELD_WG - 1) / FIELD_WG;
+  const int nwg = (nx + FIELD_WG - 1) / FIELD_WG;
+  const int nch = (nx + MCHUNK - 1) / MCHUNK;
   const int i0 = c * FIELD_WG, n = min(FIELD_WG, nx - i0);
   if (tid < n) {
     const int i = i0 + tid;
@@ -678,27 +704,10 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
     L.stage[tid] = p.dx * rho;
   }
   __syncthreads();
-  if (tid == 0) {
-    // sequential prefix of the chunk, loads batched ahead of the chain
-    double s = 0.0;
-    const int nb = n & ~15;
-    for (int q0 = 0; q0 < nb; q0 += 16) {
-      double v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = L.stage[q0 + u];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        s += v[u];
-        v[u] = s;
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) L.stage[q0 + u] = v[u];
-    }
-    for (int q = nb; q < n; ++q) {
-      s += L.stage[q];
-      L.stage[q] = s;
-    }
-    A.ctot[c] = s;
+  if (tid * MCHUNK < n) {
+    // this workgroup's chunk tid: sequential prefix and total
+    const int q0 = tid * MCHUNK;
+    A.ctot[i0 / MCHUNK + tid] = seq_prefix(L.stage + q0, min(MCHUNK, n - q0));
   }
   __syncthreads();
   // one wavefront publishes the chunk and takes the release/acquire count
@@ -707,7 +716,7 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
     if (tid == 0) {
       const int old = __hip_atomic_fetch_add(A.fcnt, 1, __ATOMIC_ACQ_REL,
                                              __HIP_MEMORY_SCOPE_AGENT);
-      L.last = (old == nch - 1);
+      L.last = (old == nwg - 1);
     }
   }
   __syncthreads();
@@ -725,7 +734,7 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
   }
   __syncthreads();
   for (int i = tid; i < nx; i += FIELD_WG)
-    A.Ml[i] = L.car[i / FIELD_WG] + ld_coherent(A.Mc + i);
+    A.Ml[i] = L.car[i / MCHUNK] + ld_coherent(A.Mc + i);
   __syncthreads();
   const double *Ml = A.Ml;
   const double Mtot = Ml[nx - 1];
@@ -761,7 +770,7 @@ __global__ __launch_bounds__(FIELD_WG) void k_field(KP p, FieldArgs A) {
 
 // The same field in one workgroup for grids of at most FIELD1_MAX columns:
 // no cross-workgroup hand-off, M_left stays in LDS.  Identical operations
-// in identical order (column sums in increasing group order, 256-site chunk
+// in identical order (column sums in increasing group order, 64-site chunk
 // prefixes, sequential carries).
 constexpr int FIELD1_MAX = 2048;
 
@@ -775,7 +784,7 @@ __device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
                                               double *car) {
   constexpr int CPT = FIELD1_MAX / NT;  // columns per thread
   const int nx = p.nx, tid = threadIdx.x;
-  const int nch = (nx + FIELD_WG - 1) / FIELD_WG;
+  const int nch = (nx + MCHUNK - 1) / MCHUNK;
   {
     double xs[CPT];
 #pragma unroll
@@ -821,27 +830,8 @@ __device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
   __syncthreads();
   if (tid < nch) {
     // sequential prefix of chunk tid
-    const int q0c = tid * FIELD_WG, n = min(FIELD_WG, nx - q0c);
-    double *st = M + q0c;
-    double s = 0.0;
-    const int nb = n & ~15;
-    for (int q0 = 0; q0 < nb; q0 += 16) {
-      double v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = st[q0 + u];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        s += v[u];
-        v[u] = s;
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) st[q0 + u] = v[u];
-    }
-    for (int q = nb; q < n; ++q) {
-      s += st[q];
-      st[q] = s;
-    }
-    car[tid] = s;
+    const int q0 = tid * MCHUNK;
+    car[tid] = seq_prefix(M + q0, min(MCHUNK, nx - q0));
   }
   __syncthreads();
   if (tid == 0) {
@@ -853,7 +843,7 @@ __device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
     }
   }
   __syncthreads();
-  for (int i = tid; i < nx; i += NT) M[i] = car[i / FIELD_WG] + M[i];
+  for (int i = tid; i < nx; i += NT) M[i] = car[i / MCHUNK] + M[i];
   __syncthreads();
   return M[nx - 1];
 }
@@ -886,7 +876,7 @@ struct AccFromMass {
 
 __global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
   __shared__ double M[FIELD1_MAX];
-  __shared__ double car[FIELD1_MAX / FIELD_WG];
+  __shared__ double car[FIELD1_MAX / MCHUNK];
   const int nx = p.nx, tid = threadIdx.x;
   const double Mtot =
       mass_to_lds<1024>(p, A.in, A.ngy, A.in_is_rho, A.rho_out, M, car);
@@ -922,7 +912,7 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
     int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
     int predict, int reg) {
   __shared__ double M[FIELD1_MAX];
-  __shared__ double car[FIELD1_MAX / FIELD_WG];
+  __shared__ double car[FIELD1_MAX / MCHUNK];
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long gsz = (long long)gridDim.x * blockDim.x;
   for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
