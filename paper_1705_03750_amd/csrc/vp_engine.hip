@@ -34,7 +34,8 @@ namespace {
 thread_local std::string g_create_error;
 
 struct Layout {
-  size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, fcnt, Mc, ctot, Ml, acc,
+  size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, fcnt, fsync, Mc, ctot,
+      Ml, acc,
       dpart, dout, tab, total;
   size_t fbytes;  // bytes per f value
   long long nb;
@@ -133,6 +134,7 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.ovf = take(64);
   L.part = take((size_t)k.ngy * k.nx * 8);
   L.fcnt = take(64);
+  L.fsync = take(64);
   L.Mc = take((size_t)k.nx * 8);
   L.ctot = take((size_t)FIELD_CHUNKS * 8);
   L.Ml = take((size_t)k.nx * 8);
@@ -161,6 +163,8 @@ struct vp_ctx {
   int64_t step;
   bool ready;
   int cur = 0;  // which of the two block-count buffers holds the live lists
+  int coop_grid = 0;     // largest co-resident grid of k_elem_field_coop
+  int64_t fsync_target = 0;  // chunks published so far through L.fsync
   int64_t reset_step = 0;  // step of the elements' last reset
   std::string err;
   std::vector<char> host_tab;  // source of the pivot-table upload
@@ -238,7 +242,11 @@ int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
 }
 
 // Field from the reconstruction's partials + kick + corrector (+ next
-// predictor) in one launch (grids of at most FIELD1_MAX columns).
+// predictor) in one launch (grids of at most FIELD1_MAX columns).  Where
+// the whole grid fits on the device at once, the shared form computes the
+// field once (its producers are the lowest workgroups, which wait on
+// nothing, so they run first whatever the residency; the consumers' wait is
+// bounded); otherwise every workgroup rebuilds the field.
 int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
                       int zero_buf) {
   const KP &k = c->k;
@@ -246,6 +254,32 @@ int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
   const long long nbz = c->L.nb;
   const long long n =
       std::max<long long>(k.E, std::min<long long>(nbz, 1 << 22));
+  const int grid = (int)grid_for(n, ELEMC_WG);
+  const int nch = (k.nx + MCHUNK - 1) / MCHUNK;
+  if (grid <= c->coop_grid && grid >= nch) {
+    int *fsync = c->at<int>(c->L.fsync);
+    if (c->fsync_target + nch > (1 << 30)) {
+      hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(256), 0, c->stream,
+                         fsync, 1LL, 0);
+      VP_LAUNCH_CHECK(c, "k_fill");
+      c->fsync_target = 0;
+    }
+    c->fsync_target += nch;
+    KP kk = k;
+    const double *part = c->at<double>(c->L.part);
+    double *Mc = c->at<double>(c->L.Mc), *ctot = c->at<double>(c->L.ctot);
+    int target = (int)c->fsync_target;
+    double *st = c->at<double>(c->L.st), *rec = c->at<double>(c->L.rec),
+           *qm = c->at<double>(c->L.qm);
+    int *cz = c->counts(zero_buf), *cr = c->counts(reg_buf);
+    long long nb = nbz;
+    int *lst = c->at<int>(c->L.lst), *flags = c->at<int>(c->L.flags);
+    hipLaunchKernelGGL(k_elem_field_coop, dim3(grid), dim3(ELEMC_WG), 0,
+                       c->stream, kk, part, Mc, ctot, fsync, target, st, rec,
+                       qm, cz, nb, cr, lst, flags, predict, reg);
+    VP_LAUNCH_CHECK(c, "k_elem_field_coop");
+    return VP_OK;
+  }
   hipLaunchKernelGGL(k_elem_field, dim3(grid_for(n, ELEMF_WG)),
                      dim3(ELEMF_WG), 0, c->stream, k,
                      c->at<double>(c->L.part), c->at<double>(c->L.st),
@@ -544,6 +578,10 @@ int check_flags(vp_ctx *c) {
     c->err = "non-finite element state or det T <= 0 met on the device";
     return VP_ENUMERIC;
   }
+  if (flags & FLAG_SYNC) {
+    c->err = "grid-wide wait of the element pass timed out";
+    return VP_EDEVICE;
+  }
   return VP_OK;
 }
 
@@ -592,6 +630,17 @@ int vp_create(const vp_params *p, void *dev_workspace, size_t bytes,
   c->t = 0.0;
   c->step = 0;
   c->ready = false;
+  // the shared-field element pass: the largest grid that is resident at once
+  {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                              dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_elem_field_coop),
+            ELEMC_WG, 0) == hipSuccess)
+      c->coop_grid = per_cu * ncu;
+  }
   // zero the whole workspace once (F padding, counts, flags, counters), then
   // the spline pivot tables and the initial elements
   int rc = fill<int>(c, c->at<int>(0), (long long)(L.total / 4), 0);

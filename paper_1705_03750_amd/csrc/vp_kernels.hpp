@@ -41,7 +41,7 @@ enum {
   S_X = 0, S_V, S_TXX, S_TXV, S_TVX, S_TVV, S_HXXX, S_HXXV, S_HXVV, S_HVXX,
   S_HVXV, S_HVVV, NSTATE
 };
-enum { FLAG_NUMERIC = 1, FLAG_WIDE = 2 };
+enum { FLAG_NUMERIC = 1, FLAG_WIDE = 2, FLAG_SYNC = 4 };
 enum { MODE_DENSITY = 0, MODE_F = 1, MODE_ASSIGN = 2, MODE_DIAG = 3 };
 
 struct KP {
@@ -923,6 +923,107 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
   const double Mtot =
       mass_to_lds<ELEMF_WG>(p, part, p.ngy, 0, nullptr, M, car);
   if (e >= p.E) return;
+  elem_kick(p, AccFromMass{p, M, Mtot}, s);
+  if (predict) elem_drift(p, s);
+  elem_store(st, E, e, s);
+  if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
+}
+
+// The same pass with the field shared instead of recomputed: the first
+// nch workgroups each sum one 64-column chunk (column sums in increasing
+// group order, the chunk's sequential prefix and total) and publish it;
+// after a grid-wide wait every workgroup adds the carries sequentially and
+// rebuilds M_left in LDS from the published chunks.  The producers are the
+// lowest-numbered workgroups and wait on nothing, so in-order dispatch runs
+// them first; the grid is launched only when it fits on the device at
+// once, and the wait is bounded (FLAG_SYNC instead of a hang).  fsync
+// counts published chunks over the run's lifetime; this launch waits for
+// target.
+constexpr int SYNC_SPIN_LIMIT = 1 << 20;  // about a second
+constexpr int ELEMC_WG = 256;
+
+__global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
+    KP p, const double *__restrict__ part, double *__restrict__ Mc,
+    double *__restrict__ ctot, int *__restrict__ fsync, int target,
+    double *__restrict__ st, double *__restrict__ rec,
+    double *__restrict__ qm, int *__restrict__ cnt_zero, long long nb_zero,
+    int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
+    int predict, int reg) {
+  __shared__ double M[FIELD1_MAX];
+  __shared__ double car[FIELD1_MAX / MCHUNK];
+  __shared__ int s_ok;
+  const int tid = threadIdx.x, nx = p.nx;
+  const int nch = (nx + MCHUNK - 1) / MCHUNK;
+  const long long gid = (long long)blockIdx.x * blockDim.x + tid;
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
+  const int e = (int)gid;
+  const size_t E = (size_t)p.E;
+  ElemState s;
+  if (e < p.E) elem_load(st, E, e, s);  // in flight during the field
+  const int c = blockIdx.x;
+  if (c < nch && tid < 64) {
+    // chunk c: one lane per column
+    const int i0 = c * MCHUNK, n = min(MCHUNK, nx - i0);
+    if (tid < n) {
+      const int i = i0 + tid;
+      double x = 0.0;
+      for (int g0 = 0; g0 < p.ngy; g0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          v[u] = (g0 + u < p.ngy) ? part[(size_t)(g0 + u) * nx + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (g0 + u < p.ngy) x += v[u];
+      }
+      M[tid] = p.dx * (p.dv * x);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (tid == 0) ctot[c] = seq_prefix(M, n);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (tid < n) Mc[i0 + tid] = M[tid];
+    // one wavefront published the chunk: release it to the grid
+    if (tid == 0)
+      __hip_atomic_fetch_add(fsync, 1, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (tid == 0) {
+    int ok = 1, spins = 0;
+    while (__hip_atomic_load(fsync, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > SYNC_SPIN_LIMIT) {
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) atomicOr(flags, FLAG_SYNC);
+    s_ok = ok;
+  }
+  __syncthreads();
+  // carries and M_left from the published chunks
+  for (int k = tid; k < nch; k += ELEMC_WG) car[k] = ld_coherent(ctot + k);
+  for (int i = tid; i < nx; i += ELEMC_WG) M[i] = ld_coherent(Mc + i);
+  __syncthreads();
+  if (tid == 0) {
+    double carry = 0.0;
+    for (int k = 0; k < nch; ++k) {
+      const double t = car[k];
+      car[k] = carry;
+      carry = carry + t;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < nx; i += ELEMC_WG) M[i] = car[i / MCHUNK] + M[i];
+  __syncthreads();
+  if (e >= p.E || !s_ok) return;
+  const double Mtot = M[nx - 1];
   elem_kick(p, AccFromMass{p, M, Mtot}, s);
   if (predict) elem_drift(p, s);
   elem_store(st, E, e, s);
