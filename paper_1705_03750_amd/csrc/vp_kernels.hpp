@@ -441,17 +441,17 @@ __device__ __forceinline__ void load_rec(const double *__restrict__ rec,
   for (int k = 0; k < RS; ++k) r.v[k] = q[k];
 }
 
-// First entries of a block's list, one per lane, requested before the
-// count is known (the row has cap >= 16 valid slots; entries beyond the
-// count are stale ids and are never used).
-__device__ __forceinline__ int list_head(const KP &p, const int *L) {
-  const int lane = threadIdx.x & 63;
-  return (lane < min(p.cap, 64)) ? L[lane] : 0;
-}
-
 // Records staged per round in a wavefront's LDS area (QSTAGE * RS doubles).
 constexpr int QSTAGE = 20;
 constexpr int RPIECES = RS / 2;  // 16-byte pieces per record
+
+// First QSTAGE entries of a block's list, one per lane, requested before
+// the count is known (the row has cap >= 16 slots; entries beyond the count
+// are stale ids and are never used).
+__device__ __forceinline__ int list_head(const KP &p, const int *L) {
+  const int lane = threadIdx.x & 63;
+  return (lane < min(p.cap, QSTAGE)) ? L[lane] : 0;
+}
 
 // Nearest element of (xP, vP) from the wave's block list, or from all
 // elements when the list overflowed or an element was too wide to list.
