@@ -54,7 +54,8 @@ class _Params(C.Structure):
                 ("force_mode", C.c_int32),
                 ("ext_a0", C.c_double), ("ext_a1", C.c_double),
                 ("ext_a2", C.c_double),
-                ("emap_max", C.c_double), ("emap_every", C.c_int32)]
+                ("emap_max", C.c_double), ("emap_every", C.c_int32),
+                ("cdyn", C.c_double)]
 
 
 _lib = None
@@ -99,6 +100,8 @@ def lib():
         L.or_set_threads.restype = C.c_int
         L.or_time.argtypes = [vp]
         L.or_time.restype = d
+        L.or_dt.argtypes = [vp]
+        L.or_dt.restype = d
         L.or_stepcount.argtypes = [vp]
         L.or_stepcount.restype = i64
         L.or_int1.argtypes = [pd, C.c_int, C.c_int, d, d]
@@ -137,7 +140,7 @@ def set_threads(n: int) -> int:
 class Oracle:
     """One oracle run.  `params` uses the engine's field names (nx, nv,
     x_min..v_max, sx, sv, G, dt, n_s, beta, force_mode, ext_a0..ext_a2,
-    emap_max, emap_every)."""
+    emap_max, emap_every, c_dyn)."""
 
     def __init__(self, **p):
         self.p = dict(p)
@@ -156,7 +159,8 @@ class Oracle:
                      int(p.get("force_mode", FORCE_SELF)),
                      ext[0], ext[1], ext[2],
                      float(p.get("emap_max", 0.0)),
-                     int(p.get("emap_every", 0)))
+                     int(p.get("emap_every", 0)),
+                     float(p.get("c_dyn", 0.0)))
         self._p = cp
         h = lib().or_create(C.byref(cp))
         if not h:
@@ -263,6 +267,12 @@ class Oracle:
     @property
     def t(self) -> float:
         return lib().or_time(self.h)
+
+    @property
+    def dt(self) -> float:
+        """The step size the next step takes (the nominal dt unless
+        c_dyn > 0)."""
+        return lib().or_dt(self.h)
 
     @property
     def stepcount(self) -> int:

@@ -45,6 +45,7 @@ struct or_ctx {
   int bnx, bnv;
   double bex, bev;
   double t;
+  double dt_cur;                 /* the step the next or_step takes first */
   int64_t step;
   int ready;
 };
@@ -647,10 +648,9 @@ static void field_from_f(or_ctx *c, const double *f, double *rho_out) {
   free(M);
 }
 
-/* Kick of section 2.4 (with the right-hand side of the T kick read as
- * T_v.(t), reading R5), then the corrector drift. */
-static void kick_and_correct(or_ctx *c) {
-  double dt = c->p.dt;
+/* Kick of section 2.4 over dt (with the right-hand side of the T kick read
+ * as T_v.(t), reading R5), then the corrector drift over dt/2. */
+static void kick_and_correct(or_ctx *c, double dt) {
   for (int e = 0; e < c->E; ++e) {
     double a, da, d2a;
     force_at_x(c, ST(c, SX_, e), &a, &da, &d2a);
@@ -669,13 +669,33 @@ static void kick_and_correct(or_ctx *c) {
   drift(c, 0.5 * dt);
 }
 
+/* Variable time step of section 2.4: dt <= C_dyn / sqrt(rho_max), the
+ * largest step that satisfies the bound, capped at the nominal dt (reading
+ * R22).  rho_max is the largest projected density dv S(i) of the given
+ * column sums, taken from 0 so that a distribution without positive
+ * density keeps the cap. */
+static double rho_max_of(const or_ctx *c, const double *S) {
+  double m = 0.0;
+  for (int i = 0; i < c->nx; ++i) {
+    double rho = c->dv * S[i];
+    if (rho > m) m = rho;
+  }
+  return m;
+}
+static double next_dt(const or_ctx *c, double rho_max) {
+  if (!(rho_max > 0.0)) return c->p.dt;
+  double d = c->p.cdyn / sqrt(rho_max);
+  return d < c->p.dt ? d : c->p.dt;
+}
+
 /* ------------------------------------------------------------------ public */
 
 or_ctx *or_create(const or_params *p) {
   if (!p || p->nx < 8 || p->nv < 8 || p->sx < 1 || p->sv < 1 ||
       p->nx % p->sx || p->nv % p->sv || !(p->dt > 0.0) ||
       !(p->x_max > p->x_min) || !(p->v_max > p->v_min) || p->n_s < 0 ||
-      !(p->beta >= 0.0 && p->beta <= 0.5))
+      !(p->beta >= 0.0 && p->beta <= 0.5) || !(p->cdyn >= 0.0) ||
+      (p->cdyn > 0.0 && p->force_mode != OR_FORCE_SELF))
     return NULL;
   or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
   if (!c) return NULL;
@@ -740,6 +760,12 @@ int or_init_conditions(or_ctx *c, const double *f0) {
   reset_elements(c);
   c->t = 0.0;
   c->step = 0;
+  c->dt_cur = c->p.dt;
+  if (c->p.cdyn > 0.0) {
+    /* the first step obeys the bound for the initial density (R22) */
+    column_sums(c, c->F, c->S);
+    c->dt_cur = next_dt(c, rho_max_of(c, c->S));
+  }
   c->ready = 1;
   return OR_OK;
 }
@@ -769,21 +795,30 @@ int or_remap(or_ctx *c) {
 
 /* One drift-kick-drift step of section 2.4: predictor drift, f at the half
  * step from the drifted elements, force, kick, corrector drift; a resample
- * after every n_s-th step (no remap at t = 0, reading R6). */
+ * after every n_s-th step (no remap at t = 0, reading R6).  With C_dyn > 0
+ * the step size follows the density bound of section 2.4: the step after
+ * this one is sized from the density of this step's half-step
+ * reconstruction (R22). */
 int or_step(or_ctx *c, int nsteps) {
   if (!c || !c->ready) return OR_ESTATE;
   if (nsteps < 0) return OR_EINVAL;
   for (int s = 0; s < nsteps; ++s) {
-    drift(c, 0.5 * c->p.dt);
+    double dt = c->dt_cur;
+    drift(c, 0.5 * dt);
     int rc = prepare_query(c);
     if (rc) return rc;
     if (c->p.force_mode == OR_FORCE_SELF) {
       reconstruct_all(c, c->f, 0, NULL);
       field_from_f(c, c->f, NULL);
     }
-    kick_and_correct(c);
+    kick_and_correct(c, dt);
     c->step += 1;
-    c->t = (double)c->step * c->p.dt;
+    if (c->p.cdyn > 0.0) {
+      c->t = c->t + dt;
+      c->dt_cur = next_dt(c, rho_max_of(c, c->S));
+    } else {
+      c->t = (double)c->step * c->p.dt;
+    }
     int remap = c->p.n_s > 0 && c->step % c->p.n_s == 0;
     if (!remap && c->p.emap_max > 0.0 && c->p.emap_every > 0 &&
         c->step % c->p.emap_every == 0) {
@@ -989,6 +1024,7 @@ int or_get_coeffs(or_ctx *c, double *out) {
 }
 
 double or_time(const or_ctx *c) { return c ? c->t : 0.0; }
+double or_dt(const or_ctx *c) { return c ? c->dt_cur : 0.0; }
 int64_t or_stepcount(const or_ctx *c) { return c ? c->step : 0; }
 
 int or_set_threads(int n) {

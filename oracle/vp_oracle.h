@@ -47,6 +47,8 @@ typedef struct or_params {
   double ext_a0, ext_a1, ext_a2;
   double emap_max;     /* adaptive remap threshold on E_map (<= 0: off) */
   int32_t emap_every;  /* steps between E_map checks (adaptive remap) */
+  double cdyn;         /* variable step dt <= cdyn / sqrt(rho_max) (<= 0:
+                          fixed dt); self-consistent force only */
 } or_params;
 
 typedef struct or_ctx or_ctx;
@@ -71,6 +73,7 @@ int or_get_assignment(or_ctx *c, int brute, int32_t *out);
 int or_get_F(or_ctx *c, double *out);
 int or_get_coeffs(or_ctx *c, double *out);
 double or_time(const or_ctx *c);
+double or_dt(const or_ctx *c);
 int64_t or_stepcount(const or_ctx *c);
 int or_set_threads(int n);
 
