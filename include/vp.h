@@ -92,6 +92,15 @@ typedef struct vp_params {
                           the fixed cadence n_s.  Not accepted by the
                           serving loop. */
   int32_t emap_every;  /* steps between E_map checks, >= 1 when enabled */
+  double c_dyn;        /* variable time step (section 2.4): > 0 makes every
+                          step min(dt, c_dyn / sqrt(rho_max)), rho_max the
+                          largest projected density -- of F_ini for the
+                          first step, of the previous step's half-step
+                          reconstruction after that; dt is then the cap.
+                          0 = fixed dt.  Self-consistent force only; not
+                          accepted by the serving loop.  Step sizes and t
+                          stay on the device (vp_time and vp_diagnostics
+                          synchronise to read them). */
 } vp_params;
 
 typedef struct vp_diag {
@@ -110,6 +119,7 @@ typedef struct vp_diag {
                          Q predicted at a site by its nearest element and by
                          one of that element's four lattice neighbours whose
                          validity window holds the site */
+  double dt;          /* size of the next step (dt unless c_dyn > 0) */
 } vp_diag;
 
 typedef struct vp_ctx vp_ctx;
@@ -172,7 +182,8 @@ int vp_get_elements(vp_ctx *ctx, double *el_dev);
 int vp_set_elements(vp_ctx *ctx, const double *el_dev);
 int vp_get_assignment(vp_ctx *ctx, int32_t *assign_dev);
 
-/* Time and step count (host values, no synchronisation). */
+/* Time and step count.  Host values without synchronisation for a fixed
+ * step; with c_dyn > 0 the time is read from the device (synchronises). */
 int vp_time(vp_ctx *ctx, double *t, int64_t *step);
 
 /* Profiling hooks.  vp_prof_begin makes every later launch of the engine

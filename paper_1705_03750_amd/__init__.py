@@ -45,7 +45,8 @@ class Params(C.Structure):
                 ("force_mode", C.c_int32),
                 ("ext_a0", C.c_double), ("ext_a1", C.c_double),
                 ("ext_a2", C.c_double), ("precision", C.c_int32),
-                ("emap_max", C.c_double), ("emap_every", C.c_int32)]
+                ("emap_max", C.c_double), ("emap_every", C.c_int32),
+                ("c_dyn", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -53,7 +54,8 @@ class Diag(C.Structure):
                 ("e_pot", C.c_double), ("energy", C.c_double),
                 ("entropy", C.c_double), ("max_det_dev", C.c_double),
                 ("t", C.c_double), ("step", C.c_int64),
-                ("overflow_blocks", C.c_int64), ("emap", C.c_double)]
+                ("overflow_blocks", C.c_int64), ("emap", C.c_double),
+                ("dt", C.c_double)]
 
 
 class Request(C.Structure):
@@ -136,7 +138,8 @@ def lib():
 def make_params(nx, nv=None, x_min=-1.0, x_max=1.0, v_min=-1.0, v_max=1.0,
                 sx=8, sv=None, G=1.0, dt=1e-3, n_s=0, beta=BETA_PAPER,
                 force_mode=FORCE_SELF, ext=(0.0, 0.0, 0.0),
-                precision="fp64", emap_max=0.0, emap_every=0) -> Params:
+                precision="fp64", emap_max=0.0, emap_every=0,
+                c_dyn=0.0) -> Params:
     prec = {"fp64": FP64, "mixed": MIXED}[precision] \
         if isinstance(precision, str) else int(precision)
     nv = nx if nv is None else nv
@@ -145,7 +148,7 @@ def make_params(nx, nv=None, x_min=-1.0, x_max=1.0, v_min=-1.0, v_max=1.0,
                   float(v_max), int(sx), int(sv), float(G), float(dt),
                   int(n_s), float(beta), int(force_mode), float(ext[0]),
                   float(ext[1]), float(ext[2]), prec, float(emap_max),
-                  int(emap_every))
+                  int(emap_every), float(c_dyn))
 
 
 def footprint(**kw) -> int:
@@ -162,7 +165,7 @@ class VlasovRun:
 
     Keyword parameters follow vp_params (nx, nv, x_min..v_max, sx, sv, G,
     dt, n_s, beta, force_mode, ext=(a0, a1, a2), precision='fp64'|'mixed',
-    emap_max, emap_every).
+    emap_max, emap_every, c_dyn).
     The workspace is one torch uint8 tensor; work is enqueued on the current
     torch stream of `device` (or `stream`, a torch.cuda.Stream)."""
 

@@ -35,7 +35,7 @@ thread_local std::string g_create_error;
 
 struct Layout {
   size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, fcnt, fsync, Mc, ctot,
-      Ml, acc,
+      rmx, clk, Ml, acc,
       dpart, dout, tab, total;
   size_t fbytes;  // bytes per f value
   long long nb;
@@ -55,7 +55,9 @@ bool params_ok(const vp_params *p) {
           p->force_mode == VP_FORCE_EXTERNAL) &&
          std::isfinite(p->G) && p->nx <= (1 << 17) && p->nv <= (1 << 17) &&
          (int64_t)(p->nx / p->sx) * (p->nv / p->sv) <= (1 << 30) &&
-         !(p->emap_max > 0.0 && p->emap_every < 1) && !std::isnan(p->emap_max);
+         !(p->emap_max > 0.0 && p->emap_every < 1) && !std::isnan(p->emap_max) &&
+         p->c_dyn >= 0.0 && std::isfinite(p->c_dyn) &&
+         !(p->c_dyn > 0.0 && p->force_mode != VP_FORCE_SELF);
 }
 
 // list capacity per 8x8 block: about twice the element count whose windows
@@ -104,6 +106,9 @@ KP make_kp(const vp_params *p) {
   k.a0 = p->ext_a0;
   k.a1 = p->ext_a1;
   k.a2 = p->ext_a2;
+  k.cdyn = p->c_dyn;
+  k.clk = nullptr;  // set by vp_create for a variable step
+  k.par = 0;
   return k;
 }
 
@@ -137,6 +142,8 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.fsync = take(64);
   L.Mc = take((size_t)k.nx * 8);
   L.ctot = take((size_t)FIELD_CHUNKS * 8);
+  L.rmx = take((size_t)FIELD_CHUNKS * 8);  // per-chunk / per-workgroup rho max
+  L.clk = take((size_t)CK_DOUBLES * 8);
   L.Ml = take((size_t)k.nx * 8);
   L.acc = take((size_t)3 * (k.nx + 8) * 8);
   L.dpart = take((size_t)3 * k.nbx * k.ngy * 8);
@@ -226,7 +233,10 @@ unsigned grid_for(long long n, int bs) {
 // count buffer `zero_buf` (-1: none).
 int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
                 int reg_buf, int zero_buf) {
-  const KP &k = c->k;
+  // a kick completes the step before the current one: it reads that step's
+  // clock slot and writes the current one
+  KP k = c->k;
+  if (kick) k.par ^= 1;
   ProfScope ps(c, kick ? PK_KICK : PK_PREDICT);
   const long long nbz = zero_buf >= 0 ? c->L.nb : 0;
   const long long n =
@@ -249,7 +259,8 @@ int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
 // bounded); otherwise every workgroup rebuilds the field.
 int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
                       int zero_buf) {
-  const KP &k = c->k;
+  KP k = c->k;
+  k.par ^= 1;  // completes the previous step (see launch_elem)
   ProfScope ps(c, PK_KICK);
   const long long nbz = c->L.nb;
   const long long n =
@@ -267,7 +278,8 @@ int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
     c->fsync_target += nch;
     KP kk = k;
     const double *part = c->at<double>(c->L.part);
-    double *Mc = c->at<double>(c->L.Mc), *ctot = c->at<double>(c->L.ctot);
+    double *Mc = c->at<double>(c->L.Mc), *ctot = c->at<double>(c->L.ctot),
+           *cmax = c->at<double>(c->L.rmx);
     int target = (int)c->fsync_target;
     double *st = c->at<double>(c->L.st), *rec = c->at<double>(c->L.rec),
            *qm = c->at<double>(c->L.qm);
@@ -275,7 +287,8 @@ int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
     long long nb = nbz;
     int *lst = c->at<int>(c->L.lst), *flags = c->at<int>(c->L.flags);
     hipLaunchKernelGGL(k_elem_field_coop, dim3(grid), dim3(ELEMC_WG), 0,
-                       c->stream, kk, part, Mc, ctot, fsync, target, st, rec,
+                       c->stream, kk, part, Mc, ctot, cmax, fsync, target, st,
+                       rec,
                        qm, cz, nb, cr, lst, flags, predict, reg);
     VP_LAUNCH_CHECK(c, "k_elem_field_coop");
     return VP_OK;
@@ -345,6 +358,7 @@ int launch_field(vp_ctx *c, const double *in, int from_part, double *rho_out,
   A.a_out = a_out;
   A.da_out = da_out;
   A.d2a_out = d2a_out;
+  A.rmx = c->at<double>(c->L.rmx);
   if (c->k.nx <= FIELD1_MAX) {
     hipLaunchKernelGGL(k_field1, dim3(1), dim3(1024), 0, c->stream, c->k, A);
     VP_LAUNCH_CHECK(c, "k_field1");
@@ -477,7 +491,8 @@ int run_steps(vp_ctx *c, int n) {
       if (rc) return rc;
     }
     c->step += 1;
-    c->t = (double)c->step * c->p.dt;
+    c->k.par = (int)(c->step & 1);
+    c->t = (double)c->step * c->p.dt;  // fixed step; the clock holds it else
     const bool remap_due = c->p.n_s > 0 && c->step % c->p.n_s == 0;
     // adaptive resampling: E_map of the post-corrector elements is checked
     // every emap_every steps (end of section 2.3.3)
@@ -568,6 +583,42 @@ int load_rows(vp_ctx *c, const double *src, int j0, int nrows) {
   return VP_OK;
 }
 
+// Variable step: the first step from the density of F_ini (column sums in
+// the reconstruction's order, then the largest dv S(i)).
+template <typename FT>
+int clock_init_t(vp_ctx *c) {
+  double *S = c->at<double>(c->L.Ml);  // scratch until the first field
+  hipLaunchKernelGGL((k_colsum_F<FT>), dim3(grid_for(c->k.nx, 256)), dim3(256),
+                     0, c->stream, c->k, c->at<FT>(c->L.F), S);
+  VP_LAUNCH_CHECK(c, "k_colsum_F");
+  hipLaunchKernelGGL(k_clock_init, dim3(1), dim3(1024), 0, c->stream, c->k, S);
+  VP_LAUNCH_CHECK(c, "k_clock_init");
+  return VP_OK;
+}
+
+int clock_init(vp_ctx *c) {
+  return c->mixed() ? clock_init_t<float>(c) : clock_init_t<double>(c);
+}
+
+// Current step size and time: host values for a fixed step, the device
+// clock's (synchronising) for a variable one.
+int read_clock(vp_ctx *c, double *dt, double *t) {
+  if (!c->k.clk) {
+    *dt = c->p.dt;
+    *t = c->t;
+    return VP_OK;
+  }
+  double slot[CK_SLOT];
+  hipError_t e = hipMemcpyAsync(slot, c->k.clk + CK_SLOT * c->k.par,
+                                sizeof(slot), hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "clock read");
+  *dt = slot[CK_DT];
+  *t = slot[CK_T];
+  return VP_OK;
+}
+
 int check_flags(vp_ctx *c) {
   int flags = 0;
   hipError_t e = hipMemcpyAsync(&flags, c->at<int>(c->L.flags), sizeof(int),
@@ -627,6 +678,7 @@ int vp_create(const vp_params *p, void *dev_workspace, size_t bytes,
   c->L = L;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ws = reinterpret_cast<char *>(dev_workspace);
+  if (p->c_dyn > 0.0) c->k.clk = c->at<double>(L.clk);
   c->t = 0.0;
   c->step = 0;
   c->ready = false;
@@ -687,9 +739,11 @@ int vp_init_conditions(vp_ctx *c, const double *f0, int f0_on_device) {
     }
   }
   if ((rc = fit_spline(c))) return rc;
-  if ((rc = launch_reset(c))) return rc;
-  c->t = 0.0;
   c->step = 0;
+  c->k.par = 0;
+  if ((rc = launch_reset(c))) return rc;
+  if (c->k.clk && (rc = clock_init(c))) return rc;
+  c->t = 0.0;
   c->reset_step = 0;
   c->ready = true;
   return VP_OK;
@@ -754,7 +808,7 @@ int vp_diagnostics(vp_ctx *c, vp_diag *out) {
   out->entropy = h[3];
   out->max_det_dev = h[4];
   out->emap = h[5];
-  out->t = c->t;
+  if ((rc = read_clock(c, &out->dt, &out->t))) return rc;
   out->step = c->step;
   out->overflow_blocks = (int64_t)ovf;
   return check_flags(c);
@@ -788,9 +842,14 @@ int vp_get_assignment(vp_ctx *c, int32_t *assign) {
 
 int vp_time(vp_ctx *c, double *t, int64_t *step) {
   if (!c) return VP_EINVAL;
-  if (t) *t = c->t;
   if (step) *step = c->step;
-  return VP_OK;
+  if (!t) return VP_OK;
+  if (!c->ready) {
+    *t = 0.0;
+    return VP_OK;
+  }
+  double dt;
+  return read_clock(c, &dt, t);
 }
 
 int vp_prof_begin(vp_ctx *c, int max_launches) {
@@ -1268,6 +1327,7 @@ int vp_server_run(vp_server *s, const vp_request *reqs, int n,
       int q = -1;
       if (rq.params.precision != s->precision || rq.nsteps < 1 ||
           !rq.f0_dev || !rq.f_out_dev || rq.params.emap_max > 0.0 ||
+          rq.params.c_dyn > 0.0 ||
           vp_footprint(&rq.params, &need) != VP_OK ||
           align_up(need) > s->pool_bytes - header_bytes(s->precision)) {
         res[r].status = VP_EINVAL;

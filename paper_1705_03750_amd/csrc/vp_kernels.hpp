@@ -52,7 +52,36 @@ struct KP {
   int force_mode;
   double a0, a1, a2;
   double tau;  // time since the elements' last reset (query-block shift)
+  // Variable time step (section 2.4), used when clk != nullptr: dt is then
+  // the cap, and the step sizes, times and tau live in the device clock
+  // below instead of the fields above.
+  double cdyn;
+  double *clk;
+  int par;  // clock slot of the current step (step count & 1)
 };
+
+// Device clock of a variable-step run: two slots of {dt, t, t_r, tau}, the
+// slot of step n holding the step size and start time of step n, the time
+// t_r of the elements' last reset and the list time tau of the last
+// registration; and rho_max of the last density the field kernels saw.
+// The element pass that completes step n reads slot n & 1 and writes slot
+// (n + 1) & 1, so no launch reads a slot it writes.
+enum { CK_DT = 0, CK_T, CK_TR, CK_TAU, CK_SLOT = 4, CK_RHO = 8,
+       CK_DOUBLES = 16 };
+
+// The step after a density with maximum rho_max: the largest dt <= cap that
+// satisfies dt <= C_dyn / sqrt(rho_max) (section 2.4); the cap when no
+// density is positive.  The cap is p.dt as the host set it.
+__device__ __forceinline__ double next_dt(const KP &p, double rho_max) {
+  if (!(rho_max > 0.0)) return p.dt;
+  const double d = p.cdyn / sqrt(rho_max);
+  return d < p.dt ? d : p.dt;
+}
+
+// List time of the current slot (kernels that read the block lists).
+__device__ __forceinline__ void clock_tau(KP &p) {
+  if (p.clk) p.tau = p.clk[CK_SLOT * p.par + CK_TAU];
+}
 
 __device__ __forceinline__ double site_x(const KP &p, int i) {
   return p.x_min + ((double)i + 0.5) * p.dx;
@@ -322,11 +351,35 @@ __global__ __launch_bounds__(256) void k_elem(
   const long long gsz = (long long)gridDim.x * blockDim.x;
   for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
   const int e = (int)gid;
+  // variable step: this step's dt from the clock; after a kick, the next
+  // step's from the density the field kernel saw
+  double t1 = 0.0, tr = 0.0, dtn = p.dt;
+  if (p.clk) {
+    const double *ck = p.clk + CK_SLOT * p.par;
+    if (kick) dtn = next_dt(p, p.clk[CK_RHO]);  // p.dt is still the cap
+    p.dt = ck[CK_DT];
+    p.h = 0.5 * p.dt;
+    t1 = ck[CK_T];
+    tr = ck[CK_TR];
+    if (kick) t1 = t1 + p.dt;
+    const double hp = (predict && drift) ? 0.5 * (kick ? dtn : p.dt) : 0.0;
+    p.tau = (t1 + hp) - tr;
+    if (gid == 0) {
+      double *cw = p.clk + CK_SLOT * (kick ? p.par ^ 1 : p.par);
+      if (kick) {
+        cw[CK_DT] = dtn;
+        cw[CK_T] = t1;
+        cw[CK_TR] = tr;
+      }
+      cw[CK_TAU] = p.tau;
+    }
+  }
   if (e >= p.E) return;
   const size_t E = (size_t)p.E;
   ElemState s;
   elem_load(st, E, e, s);
   if (kick) elem_kick(p, AccTable{acc, p.nx + 8}, s);
+  if (p.clk && kick) p.h = 0.5 * dtn;
   if (predict && drift) elem_drift(p, s);
   if (kick || (predict && drift)) elem_store(st, E, e, s);
   if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
@@ -341,6 +394,10 @@ __global__ __launch_bounds__(256) void k_elem_reset(KP p,
   const long long gsz = (long long)gridDim.x * blockDim.x;
   for (long long b = gid; b < nb; b += gsz) cnt[b] = 0;
   const int e = (int)gid;
+  if (p.clk && gid == 0) {
+    double *ck = p.clk + CK_SLOT * p.par;
+    ck[CK_TR] = ck[CK_T];
+  }
   if (e >= p.E) return;
   const size_t E = (size_t)p.E;
   const int k = e % p.mx, l = e / p.mx;
@@ -659,6 +716,7 @@ struct FieldArgs {
   double *Ml;         // cumulative mass [nx]
   double *acc;        // a, a', a'' on [-4, nx + 3]
   double *rho_out, *a_out, *da_out, *d2a_out;  // optional
+  double *rmx;        // per-workgroup largest rho [nwg] (variable step)
 };
 
 __device__ __forceinline__ double ld_coherent(const double *q) {
@@ -667,10 +725,18 @@ __device__ __forceinline__ double ld_coherent(const double *q) {
       __HIP_MEMORY_SCOPE_AGENT));
 }
 
+// Largest value over the 64 lanes of a wavefront (order-free: max is exact).
+__device__ __forceinline__ double wave_max(double m) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  return m;
+}
+
 // LDS of one field workgroup
 struct FieldLds {
   double stage[FIELD_WG];
   double car[FIELD_CHUNKS];
+  double red[FIELD_WG / 64];
   int last;
 };
 
@@ -680,6 +746,7 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
   const int nwg = (nx + FIELD_WG - 1) / FIELD_WG;
   const int nch = (nx + MCHUNK - 1) / MCHUNK;
   const int i0 = c * FIELD_WG, n = min(FIELD_WG, nx - i0);
+  double m = 0.0;
   if (tid < n) {
     const int i = i0 + tid;
     double x;
@@ -702,6 +769,11 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
     const double rho = A.in_is_rho ? x : p.dv * x;
     if (A.rho_out) A.rho_out[i] = rho;
     L.stage[tid] = p.dx * rho;
+    m = fmax(m, rho);
+  }
+  if (p.clk) {
+    m = wave_max(m);
+    if ((tid & 63) == 0) L.red[tid >> 6] = m;
   }
   __syncthreads();
   if (tid * MCHUNK < n) {
@@ -714,6 +786,11 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
   if (tid < 64) {
     for (int q = tid; q < n; q += 64) A.Mc[i0 + q] = L.stage[q];
     if (tid == 0) {
+      if (p.clk) {
+        double w = 0.0;
+        for (int k = 0; k < FIELD_WG / 64; ++k) w = fmax(w, L.red[k]);
+        A.rmx[c] = w;
+      }
       const int old = __hip_atomic_fetch_add(A.fcnt, 1, __ATOMIC_ACQ_REL,
                                              __HIP_MEMORY_SCOPE_AGENT);
       L.last = (old == nwg - 1);
@@ -723,6 +800,11 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
   if (!L.last) return;
   // the last chunk: carries, M_left, force
   for (int k = tid; k < nch; k += FIELD_WG) L.car[k] = ld_coherent(A.ctot + k);
+  if (p.clk && tid == 0) {
+    double w = 0.0;
+    for (int k = 0; k < nwg; ++k) w = fmax(w, ld_coherent(A.rmx + k));
+    p.clk[CK_RHO] = w;
+  }
   __syncthreads();
   if (tid == 0) {
     double carry = 0.0;
@@ -775,13 +857,15 @@ __global__ __launch_bounds__(FIELD_WG) void k_field(KP p, FieldArgs A) {
 constexpr int FIELD1_MAX = 2048;
 
 // M_left of every column into LDS M[0, nx) (NT threads, the whole
-// workgroup); returns M_tot.  `in` holds the row-group partials (ngy > 0)
+// workgroup); returns M_tot.  With a variable step (p.clk), also the
+// largest rho (from 0) into rmax, red[] holding NT/64 LDS doubles.  `in` holds the row-group partials (ngy > 0)
 // or rho (ngy == 0).
 template <int NT>
 __device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
                                               int ngy, int in_is_rho,
                                               double *rho_out, double *M,
-                                              double *car) {
+                                              double *car, double *red,
+                                              double &rmax) {
   constexpr int CPT = FIELD1_MAX / NT;  // columns per thread
   const int nx = p.nx, tid = threadIdx.x;
   const int nch = (nx + MCHUNK - 1) / MCHUNK;
@@ -817,6 +901,7 @@ __device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
         if (i < nx) xs[c] = in[i];
       }
     }
+    double m = 0.0;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int i = tid + c * NT;
@@ -824,10 +909,21 @@ __device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
         const double rho = in_is_rho ? xs[c] : p.dv * xs[c];
         if (rho_out) rho_out[i] = rho;
         M[i] = p.dx * rho;
+        m = fmax(m, rho);
       }
+    }
+    if (p.clk) {
+      m = wave_max(m);
+      if ((tid & 63) == 0) red[tid >> 6] = m;
     }
   }
   __syncthreads();
+  if (p.clk) {
+    double m = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) m = fmax(m, red[w]);
+    rmax = m;
+  }
   if (tid < nch) {
     // sequential prefix of chunk tid
     const int q0 = tid * MCHUNK;
@@ -877,9 +973,12 @@ struct AccFromMass {
 __global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
   __shared__ double M[FIELD1_MAX];
   __shared__ double car[FIELD1_MAX / MCHUNK];
+  __shared__ double red[1024 / 64];
   const int nx = p.nx, tid = threadIdx.x;
-  const double Mtot =
-      mass_to_lds<1024>(p, A.in, A.ngy, A.in_is_rho, A.rho_out, M, car);
+  double rmax = 0.0;
+  const double Mtot = mass_to_lds<1024>(p, A.in, A.ngy, A.in_is_rho,
+                                        A.rho_out, M, car, red, rmax);
+  if (p.clk && tid == 0) p.clk[CK_RHO] = rmax;
   for (int i = tid; i < nx; i += 1024) A.Ml[i] = M[i];
   const int n8 = nx + 8;
   for (int q = tid; q < n8; q += 1024) {
@@ -895,6 +994,30 @@ __global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
       A.d2a_out[i] = d2a;
     }
   }
+}
+
+// Clock of the element pass that completes a step (kick + corrector,
+// optionally the next predictor).  Fixed step: returns dt and leaves p.
+// Variable step: p.dt and p.h become this step's, p.tau the list time of
+// the next predictor; returns the next step's dt (from rmax, the density's
+// maximum); `writer` stores the next slot.
+__device__ __forceinline__ double elem_clock(KP &p, double rmax, int predict,
+                                             bool writer) {
+  if (!p.clk) return p.dt;
+  const double *ck = p.clk + CK_SLOT * p.par;
+  const double dtn = next_dt(p, rmax);  // p.dt is still the cap
+  p.dt = ck[CK_DT];
+  p.h = 0.5 * p.dt;
+  const double t1 = ck[CK_T] + p.dt, tr = ck[CK_TR];
+  p.tau = (t1 + (predict ? 0.5 * dtn : 0.0)) - tr;
+  if (writer) {
+    double *cw = p.clk + CK_SLOT * (p.par ^ 1);
+    cw[CK_DT] = dtn;
+    cw[CK_T] = t1;
+    cw[CK_TR] = tr;
+    cw[CK_TAU] = p.tau;
+  }
+  return dtn;
 }
 
 // Field and element pass in one launch (grids of at most FIELD1_MAX
@@ -913,6 +1036,7 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
     int predict, int reg) {
   __shared__ double M[FIELD1_MAX];
   __shared__ double car[FIELD1_MAX / MCHUNK];
+  __shared__ double red[ELEMF_WG / 64];
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long gsz = (long long)gridDim.x * blockDim.x;
   for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
@@ -920,11 +1044,16 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
   const size_t E = (size_t)p.E;
   ElemState s;
   if (e < p.E) elem_load(st, E, e, s);  // in flight during the field
-  const double Mtot =
-      mass_to_lds<ELEMF_WG>(p, part, p.ngy, 0, nullptr, M, car);
+  double rmax = 0.0;
+  const double Mtot = mass_to_lds<ELEMF_WG>(p, part, p.ngy, 0, nullptr, M,
+                                            car, red, rmax);
+  const double dtn = elem_clock(p, rmax, predict, gid == 0);
   if (e >= p.E) return;
   elem_kick(p, AccFromMass{p, M, Mtot}, s);
-  if (predict) elem_drift(p, s);
+  if (predict) {
+    p.h = 0.5 * dtn;
+    elem_drift(p, s);
+  }
   elem_store(st, E, e, s);
   if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
 }
@@ -944,7 +1073,8 @@ constexpr int ELEMC_WG = 256;
 
 __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
     KP p, const double *__restrict__ part, double *__restrict__ Mc,
-    double *__restrict__ ctot, int *__restrict__ fsync, int target,
+    double *__restrict__ ctot, double *__restrict__ cmax,
+    int *__restrict__ fsync, int target,
     double *__restrict__ st, double *__restrict__ rec,
     double *__restrict__ qm, int *__restrict__ cnt_zero, long long nb_zero,
     int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
@@ -952,6 +1082,7 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
   __shared__ double M[FIELD1_MAX];
   __shared__ double car[FIELD1_MAX / MCHUNK];
   __shared__ int s_ok;
+  __shared__ double s_rmax;
   const int tid = threadIdx.x, nx = p.nx;
   const int nch = (nx + MCHUNK - 1) / MCHUNK;
   const long long gid = (long long)blockIdx.x * blockDim.x + tid;
@@ -965,6 +1096,7 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
   if (c < nch && tid < 64) {
     // chunk c: one lane per column
     const int i0 = c * MCHUNK, n = min(MCHUNK, nx - i0);
+    double m = 0.0;
     if (tid < n) {
       const int i = i0 + tid;
       double x = 0.0;
@@ -977,7 +1109,14 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
         for (int u = 0; u < 16; ++u)
           if (g0 + u < p.ngy) x += v[u];
       }
-      M[tid] = p.dx * (p.dv * x);
+      const double rho = p.dv * x;
+      M[tid] = p.dx * rho;
+      m = fmax(m, rho);
+    }
+    if (p.clk) {
+      // the chunk's largest density, published with the chunk
+      m = wave_max(m);
+      if (tid == 0) cmax[c] = m;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1018,14 +1157,24 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
       car[k] = carry;
       carry = carry + t;
     }
+    if (p.clk) {
+      double m = 0.0;
+      for (int k = 0; k < nch; ++k) m = fmax(m, ld_coherent(cmax + k));
+      s_rmax = m;
+    }
   }
   __syncthreads();
   for (int i = tid; i < nx; i += ELEMC_WG) M[i] = car[i / MCHUNK] + M[i];
   __syncthreads();
-  if (e >= p.E || !s_ok) return;
+  if (!s_ok) return;
+  const double dtn = elem_clock(p, p.clk ? s_rmax : 0.0, predict, gid == 0);
+  if (e >= p.E) return;
   const double Mtot = M[nx - 1];
   elem_kick(p, AccFromMass{p, M, Mtot}, s);
-  if (predict) elem_drift(p, s);
+  if (predict) {
+    p.h = 0.5 * dtn;
+    elem_drift(p, s);
+  }
   elem_store(st, E, e, s);
   if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
 }
@@ -1167,6 +1316,7 @@ __global__ __launch_bounds__(512) void k_recon(
     int *__restrict__ aout, double *__restrict__ dpart,
     unsigned long long *__restrict__ ovf) {
   const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
+  clock_tau(p);
   recon_tile<FT, MODE>(p, rec, qm, cnt, lst, flags, F, part, fout, aout, dpart,
                        ovf, t % p.nbx, t / p.nbx);
 }
@@ -1255,6 +1405,7 @@ __global__ __launch_bounds__(512) void k_remap_eval(
     const FT *__restrict__ C, FT *__restrict__ Fout,
     unsigned long long *__restrict__ ovf) {
   const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
+  clock_tau(p);
   remap_tile<FT, TO_F>(p, rec, qm, cnt, lst, flags, C, Fout, ovf, t % p.nbx,
                        t / p.nbx);
 }
@@ -1694,6 +1845,54 @@ __global__ __launch_bounds__(256) void k_load_f0(KP p,
     const int j = j0 + jr;
     const bool ring = (i == 0 || j == 0 || i == p.nx - 1 || j == p.nv - 1);
     F[(long)(j + PV) * p.pitch + (i + PX)] = ring ? (FT)0 : (FT)src[q];
+  }
+}
+
+// Variable step, first step (section 2.4): column sums of F_ini, one thread
+// per column, in the fixed order of the reconstruction's density (8-row
+// strips sequential, strips added in order into 64-row groups, groups in
+// increasing order; boundaries on rows congruent to ov), into S[nx].
+template <typename FT>
+__global__ __launch_bounds__(256) void k_colsum_F(KP p,
+                                                  const FT *__restrict__ F,
+                                                  double *__restrict__ S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.nx) return;
+  const FT *col = F + (long)PV * p.pitch + PX + i;
+  double tot = 0.0, grp = 0.0, strip = 0.0;
+  for (int j = 0; j < p.nv; ++j) {
+    strip += (double)col[(long)j * p.pitch];
+    const int r = j + 1 - p.ov;
+    const bool last = (j == p.nv - 1);
+    if ((r & 7) == 0 || last) {
+      grp += strip;
+      strip = 0.0;
+    }
+    if ((r & 63) == 0 || last) {
+      tot += grp;
+      grp = 0.0;
+    }
+  }
+  S[i] = tot;
+}
+
+// The clock at t = 0: slot 0 = {dt_0, 0, 0, 0}, dt_0 from the largest
+// dv S(i); slot 1 cleared.  One workgroup.
+__global__ __launch_bounds__(1024) void k_clock_init(KP p,
+                                                     const double *__restrict__ S) {
+  __shared__ double red[1024 / 64];
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  for (int i = tid; i < p.nx; i += 1024) m = fmax(m, p.dv * S[i]);
+  m = wave_max(m);
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double r = 0.0;
+    for (int w = 0; w < 1024 / 64; ++w) r = fmax(r, red[w]);
+    for (int q = 0; q < CK_DOUBLES; ++q) p.clk[q] = 0.0;
+    p.clk[CK_DT] = next_dt(p, r);
+    p.clk[CK_RHO] = r;
   }
 }
 

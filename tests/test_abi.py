@@ -44,7 +44,11 @@ def test_footprint_and_validation(vp):
                 dict(nx=64, sx=4, dt=0.0),        # dt <= 0
                 dict(nx=64, sx=4, dt=1e-3, x_min=1.0, x_max=1.0),
                 dict(nx=64, sx=4, dt=1e-3, n_s=-1),
-                dict(nx=64, sx=4, dt=1e-3, precision=7)):
+                dict(nx=64, sx=4, dt=1e-3, precision=7),
+                dict(nx=64, sx=4, dt=1e-3, c_dyn=-0.5),
+                dict(nx=64, sx=4, dt=1e-3, c_dyn=float("inf")),
+                # the variable step needs the self-consistent density
+                dict(nx=64, sx=4, dt=1e-3, c_dyn=0.1, force_mode=1)):
         with pytest.raises(vp.VPError) as ei:
             vp.footprint(**bad)
         assert ei.value.code == vp.EINVAL
