@@ -24,6 +24,8 @@ _LIB_PATH = os.path.join(_OUTDIR, "liboracle.so")
 
 FORCE_SELF = 0
 FORCE_EXTERNAL = 1
+BC_ISOLATED = 0
+BC_PERIODIC = 1
 SCHEME_TRANSPORT = 0
 SCHEME_REMAP = 1
 BETA_DEFAULT = 0.5 * (1.0 - math.sqrt(3.0) / 2.0)
@@ -55,7 +57,7 @@ class _Params(C.Structure):
                 ("ext_a0", C.c_double), ("ext_a1", C.c_double),
                 ("ext_a2", C.c_double),
                 ("emap_max", C.c_double), ("emap_every", C.c_int32),
-                ("cdyn", C.c_double)]
+                ("cdyn", C.c_double), ("bc", C.c_int32)]
 
 
 _lib = None
@@ -91,6 +93,7 @@ def lib():
             ("or_get_F", [vp, pd]),
             ("or_get_coeffs", [vp, pd]),
             ("or_spline_fit", [C.c_int, C.c_int, pd, pd]),
+            ("or_spline_fit_periodic", [C.c_int, C.c_int, pd, pd]),
             ("or_inverse_map", [pd, d, d, d, d, pd]),
         ]:
             fn = getattr(L, name)
@@ -104,12 +107,13 @@ def lib():
         L.or_dt.restype = d
         L.or_stepcount.argtypes = [vp]
         L.or_stepcount.restype = i64
-        L.or_int1.argtypes = [pd, C.c_int, C.c_int, d, d]
-        L.or_int1.restype = d
+        for name in ("or_int1", "or_int1_periodic", "or_spline_eval",
+                     "or_spline_eval_periodic"):
+            fn = getattr(L, name)
+            fn.argtypes = [pd, C.c_int, C.c_int, d, d]
+            fn.restype = d
         L.or_W.argtypes = [d]
         L.or_W.restype = d
-        L.or_spline_eval.argtypes = [pd, C.c_int, C.c_int, d, d]
-        L.or_spline_eval.restype = d
         L.or_tsc.argtypes = [pd, C.c_int, d]
         L.or_tsc.restype = d
         _lib = L
@@ -140,7 +144,7 @@ def set_threads(n: int) -> int:
 class Oracle:
     """One oracle run.  `params` uses the engine's field names (nx, nv,
     x_min..v_max, sx, sv, G, dt, n_s, beta, force_mode, ext_a0..ext_a2,
-    emap_max, emap_every, c_dyn)."""
+    emap_max, emap_every, c_dyn, bc)."""
 
     def __init__(self, **p):
         self.p = dict(p)
@@ -160,7 +164,8 @@ class Oracle:
                      ext[0], ext[1], ext[2],
                      float(p.get("emap_max", 0.0)),
                      int(p.get("emap_every", 0)),
-                     float(p.get("c_dyn", 0.0)))
+                     float(p.get("c_dyn", 0.0)),
+                     int(p.get("bc", BC_ISOLATED)))
         self._p = cp
         h = lib().or_create(C.byref(cp))
         if not h:
@@ -280,28 +285,31 @@ class Oracle:
 
 
 # --- primitives -----------------------------------------------------------
-def int1(F, sx: float, sv: float) -> float:
+def int1(F, sx: float, sv: float, periodic: bool = False) -> float:
     F = _f64(F)
     nv, nx = F.shape
-    return lib().or_int1(_dp(F), nx, nv, float(sx), float(sv))
+    fn = lib().or_int1_periodic if periodic else lib().or_int1
+    return fn(_dp(F), nx, nv, float(sx), float(sv))
 
 
 def W(x: float) -> float:
     return lib().or_W(float(x))
 
 
-def spline_fit(F) -> np.ndarray:
+def spline_fit(F, periodic: bool = False) -> np.ndarray:
     F = _f64(F)
     nv, nx = F.shape
     Cc = np.empty_like(F)
-    _check(lib().or_spline_fit(nx, nv, _dp(F), _dp(Cc)), "spline_fit")
+    fn = lib().or_spline_fit_periodic if periodic else lib().or_spline_fit
+    _check(fn(nx, nv, _dp(F), _dp(Cc)), "spline_fit")
     return Cc
 
 
-def spline_eval(Cc, sx: float, sv: float) -> float:
+def spline_eval(Cc, sx: float, sv: float, periodic: bool = False) -> float:
     Cc = _f64(Cc)
     nv, nx = Cc.shape
-    return lib().or_spline_eval(_dp(Cc), nx, nv, float(sx), float(sv))
+    fn = lib().or_spline_eval_periodic if periodic else lib().or_spline_eval
+    return fn(_dp(Cc), nx, nv, float(sx), float(sv))
 
 
 def inverse_map(el12, dxm, dvm, xP, vP):

@@ -41,6 +41,9 @@ struct or_ctx {
   double *S;                     /* column sums of f [nx] */
   double *Ml;                    /* cumulative mass M_left [nx] */
   double Mtot;
+  int per;                       /* periodic in x (reading R23) */
+  double Lx;                     /* period x_max - x_min */
+  double Bbar;                   /* mean of the periodic field sum B(i) */
   int *bstart, *bitem;           /* bucket grid (counting sort) */
   int bnx, bnv;
   double bex, bev;
@@ -86,11 +89,26 @@ static void reset_elements(or_ctx *c) {
   }
 }
 
+/* Periodic x (reading R23): a position that a drift moved out of
+ * [x_min, x_max) re-enters from the other side (one period at most; a sum
+ * that rounds onto the far edge is put on x_min). */
+static double wrap_x(const or_ctx *c, double x) {
+  if (x < c->p.x_min) {
+    x = x + c->Lx;
+    if (x >= c->p.x_max) x = c->p.x_min;
+  } else if (x >= c->p.x_max) {
+    x = x - c->Lx;
+    if (x < c->p.x_min) x = c->p.x_min;
+  }
+  return x;
+}
+
 /* Drift over h (section 2.4, predictor and corrector): positions move with
  * the velocities, T_x. with T_v., H_x with H_v. */
 static void drift(or_ctx *c, double h) {
   for (int e = 0; e < c->E; ++e) {
     ST(c, SX_, e) = fma(h, ST(c, SV_, e), ST(c, SX_, e));
+    if (c->per) ST(c, SX_, e) = wrap_x(c, ST(c, SX_, e));
     ST(c, TXX, e) = fma(h, ST(c, TVX, e), ST(c, TXX, e));
     ST(c, TXV, e) = fma(h, ST(c, TVV, e), ST(c, TXV, e));
     ST(c, HXXX, e) = fma(h, ST(c, HVXX, e), ST(c, HXXX, e));
@@ -127,8 +145,16 @@ static int precompute(or_ctx *c) {
  * R8: the first-order Lagrangian offset stays inside one element spacing). */
 static int inv_map(double xm, double vm, double axx, double axv, double avx,
                    double avv, const double *h6, double dxm, double dvm,
-                   double xP, double vP, double *dqx, double *dqv) {
+                   double xP, double vP, double Lx, double *dqx, double *dqv) {
   double dx = xP - xm, dv = vP - vm;
+  if (Lx > 0.0) {
+    /* periodic x: the nearest image of the element (reading R23) */
+    double hL = 0.5 * Lx;
+    if (dx > hL)
+      dx = dx - Lx;
+    else if (dx < -hL)
+      dx = dx + Lx;
+  }
   double lx = fma(axx, dx, axv * dv);
   double lv = fma(avx, dx, avv * dv);
   int valid = fabs(lx) < dxm && fabs(lv) < dvm;
@@ -145,8 +171,8 @@ static int elem_map(const or_ctx *c, int e, double xP, double vP, double *dqx,
   double h6[6] = {ST(c, HXXX, e), ST(c, HXXV, e), ST(c, HXVV, e),
                   ST(c, HVXX, e), ST(c, HVXV, e), ST(c, HVVV, e)};
   return inv_map(ST(c, SX_, e), ST(c, SV_, e), AM(c, 0, e), AM(c, 1, e),
-                 AM(c, 2, e), AM(c, 3, e), h6, c->dxm, c->dvm, xP, vP, dqx,
-                 dqv);
+                 AM(c, 2, e), AM(c, 3, e), h6, c->dxm, c->dvm, xP, vP,
+                 c->per ? c->Lx : 0.0, dqx, dqv);
 }
 
 /* Squared Lagrangian distance of eq. (distdef), normalised by the element
@@ -198,6 +224,13 @@ static int build_buckets(or_ctx *c) {
   if (ex < Lx / cap) ex = Lx / cap;
   if (ev < Lv / cap) ev = Lv / cap;
   int bnx = (int)ceil(Lx / ex), bnv = (int)ceil(Lv / ev);
+  if (c->per) {
+    /* periodic x: equal buckets no narrower than the reach, so that the
+     * wrapped neighbouring buckets hold every valid element */
+    bnx = (int)floor(Lx / ex);
+    if (bnx < 1) bnx = 1;
+    ex = Lx / bnx;
+  }
   if (bnx < 1) bnx = 1;
   if (bnv < 1) bnv = 1;
   free(c->bstart);
@@ -238,9 +271,19 @@ static int query_bucketed(const or_ctx *c, double xP, double vP, double *bdqx,
   int bv = (int)floor((vP - c->p.v_min) / c->bev);
   int best = -1;
   double bd = INFINITY;
+  if (bx < 0) bx = 0;
+  if (bx > c->bnx - 1) bx = c->bnx - 1;
+  /* periodic x with fewer than 3 buckets: visit each bucket once */
+  int ilo = bx - 1, ihi = bx + 1;
+  if (c->per && c->bnx < 3) {
+    ilo = 0;
+    ihi = c->bnx - 1;
+  }
   for (int jb = bv - 1; jb <= bv + 1; ++jb) {
     if (jb < 0 || jb >= c->bnv) continue;
-    for (int ib = bx - 1; ib <= bx + 1; ++ib) {
+    for (int iu = ilo; iu <= ihi; ++iu) {
+      int ib = iu;
+      if (c->per) ib = (iu + c->bnx) % c->bnx;
       if (ib < 0 || ib >= c->bnx) continue;
       int b = jb * c->bnx + ib;
       for (int q = c->bstart[b]; q < c->bstart[b + 1]; ++q) {
@@ -262,9 +305,19 @@ static int query_bucketed(const or_ctx *c, double xP, double vP, double *bdqx,
 
 /* ---------------------------------------------------------- interpolation */
 
-static double Fat(const double *F, int nx, int nv, int i, int j) {
+static double Fat(const double *F, int nx, int nv, int i, int j, int per) {
+  if (per) i = ((i % nx) + nx) % nx;
   if (i < 0 || i >= nx || j < 0 || j >= nv) return 0.0;
   return F[(size_t)j * nx + i];
+}
+
+/* Periodic x (reading R23): interpolation positions are clamped to
+ * [-12, nx + 11] sites (only elements far outside their validity could
+ * reach beyond) and the data repeat with period nx. */
+static double clamp_periodic(double sx, int nx) {
+  if (sx < -12.0) return -12.0;
+  if (sx > (double)nx + 11.0) return (double)nx + 11.0;
+  return sx;
 }
 
 /* Six-point second-order interpolation of section 2.2.1, eq. (int1), at
@@ -272,8 +325,14 @@ static double Fat(const double *F, int nx, int nv, int i, int j) {
  * F(i_n-1) terms carry a minus sign and the v-row uses F(i_n, j_n-1): the
  * Lagrange form of the quadratic through the cross (reading R10; the printed
  * signs make the weights sum to 1.25).  i_n rounds half up (reading R11). */
-double or_int1(const double *F, int nx, int nv, double sx, double sv) {
-  if (!(sx > -4.0 && sx < nx + 3.0 && sv > -4.0 && sv < nv + 3.0)) return 0.0;
+static double int1_eval(const double *F, int nx, int nv, double sx,
+                        double sv, int per) {
+  if (per) {
+    sx = clamp_periodic(sx, nx);
+    if (!(sv > -4.0 && sv < nv + 3.0)) return 0.0;
+  } else if (!(sx > -4.0 && sx < nx + 3.0 && sv > -4.0 && sv < nv + 3.0)) {
+    return 0.0;
+  }
   double fin = floor(sx + 0.5), fjn = floor(sv + 0.5);
   double fic = floor(sx), fjc = floor(sv);
   int in = (int)fin, jn = (int)fjn, ic = (int)fic, jc = (int)fjc;
@@ -283,16 +342,26 @@ double or_int1(const double *F, int nx, int nv, double sx, double sv) {
   double wxp = hx * (1.0 + dqx), wxm = hx * (1.0 - dqx);
   double wvp = hv * (1.0 + dqv), wvm = hv * (1.0 - dqv);
   double wc = dqx * dqv;
-  double cross = ((Fat(F, nx, nv, ic + 1, jc + 1) + Fat(F, nx, nv, ic, jc)) -
-                  Fat(F, nx, nv, ic + 1, jc)) -
-                 Fat(F, nx, nv, ic, jc + 1);
-  double f = Fat(F, nx, nv, in, jn) * w0;
-  f = fma(Fat(F, nx, nv, in + 1, jn), wxp, f);
-  f = fma(-Fat(F, nx, nv, in - 1, jn), wxm, f);
-  f = fma(Fat(F, nx, nv, in, jn + 1), wvp, f);
-  f = fma(-Fat(F, nx, nv, in, jn - 1), wvm, f);
+  double cross = ((Fat(F, nx, nv, ic + 1, jc + 1, per) +
+                   Fat(F, nx, nv, ic, jc, per)) -
+                  Fat(F, nx, nv, ic + 1, jc, per)) -
+                 Fat(F, nx, nv, ic, jc + 1, per);
+  double f = Fat(F, nx, nv, in, jn, per) * w0;
+  f = fma(Fat(F, nx, nv, in + 1, jn, per), wxp, f);
+  f = fma(-Fat(F, nx, nv, in - 1, jn, per), wxm, f);
+  f = fma(Fat(F, nx, nv, in, jn + 1, per), wvp, f);
+  f = fma(-Fat(F, nx, nv, in, jn - 1, per), wvm, f);
   f = fma(cross, wc, f);
   return f;
+}
+
+double or_int1(const double *F, int nx, int nv, double sx, double sv) {
+  return int1_eval(F, nx, nv, sx, sv, 0);
+}
+
+double or_int1_periodic(const double *F, int nx, int nv, double sx,
+                        double sv) {
+  return int1_eval(F, nx, nv, sx, sv, 1);
 }
 
 /* Cubic B-spline interpolation with the edge conditions of section 2.2.2:
@@ -320,6 +389,81 @@ static void thomas_line(int n, const double *rhs_in, size_t istride,
     out[(size_t)i * ostride] = dp[i] - cp[i] * out[(size_t)(i + 1) * ostride];
 }
 
+/* Periodic line (reading R23): the cyclic system c(i-1) + 4 c(i) + c(i+1)
+ * = 6 F(i), indices mod n, by the Sherman-Morrison form of Thomas
+ * elimination: with gamma = -4 the corner entries move into the rank-one
+ * term u v^T, u = (gamma, 0.., 0, 1), v = (1, 0.., 0, 1/gamma), leaving the
+ * tridiagonal B with diagonal (8, 4, .., 4, 4.25) and unit off-diagonals.
+ * Solve B y = 6 F and B z = u, then c = y - [(v.y) / (1 + v.z)] z.  n >= 3. */
+static void thomas_plain(int n, const double *b, const double *rhs,
+                         double *out, double *cp, double *dp) {
+  double rinv = 1.0 / b[0];
+  cp[0] = rinv;
+  dp[0] = rhs[0] * rinv;
+  for (int i = 1; i < n; ++i) {
+    double den = b[i] - cp[i - 1];
+    rinv = 1.0 / den;
+    cp[i] = rinv;
+    dp[i] = (rhs[i] - dp[i - 1]) * rinv;
+  }
+  out[n - 1] = dp[n - 1];
+  for (int i = n - 2; i >= 0; --i) out[i] = dp[i] - cp[i] * out[i + 1];
+}
+
+static int cyclic_line(int n, const double *rhs_in, size_t istride,
+                       double *out, size_t ostride) {
+  double *b = (double *)malloc(sizeof(double) * n);
+  double *r = (double *)malloc(sizeof(double) * n);
+  double *u = (double *)calloc(n, sizeof(double));
+  double *y = (double *)malloc(sizeof(double) * n);
+  double *z = (double *)malloc(sizeof(double) * n);
+  double *cp = (double *)malloc(sizeof(double) * n);
+  double *dp = (double *)malloc(sizeof(double) * n);
+  int ok = b && r && u && y && z && cp && dp;
+  if (ok) {
+    for (int i = 0; i < n; ++i) {
+      b[i] = 4.0;
+      r[i] = 6.0 * rhs_in[(size_t)i * istride];
+    }
+    b[0] = 8.0;       /* 4 - gamma */
+    b[n - 1] = 4.25;  /* 4 - 1 * 1 / gamma */
+    u[0] = -4.0;
+    u[n - 1] = 1.0;
+    thomas_plain(n, b, r, y, cp, dp);
+    thomas_plain(n, b, u, z, cp, dp);
+    double num = y[0] - 0.25 * y[n - 1];
+    double den = (1.0 + z[0]) - 0.25 * z[n - 1];
+    double fact = num / den;
+    for (int i = 0; i < n; ++i) out[(size_t)i * ostride] = y[i] - fact * z[i];
+  }
+  free(b);
+  free(r);
+  free(u);
+  free(y);
+  free(z);
+  free(cp);
+  free(dp);
+  return ok ? OR_OK : OR_ENOMEM;
+}
+
+/* Periodic in x, edge conditions of section 2.2.2 in v (reading R23). */
+int or_spline_fit_periodic(int nx, int nv, const double *F, double *C) {
+  if (nx < 3 || nv < 2) return OR_EINVAL;
+  double *cp = (double *)malloc(sizeof(double) * nv);
+  double *dp = (double *)malloc(sizeof(double) * nv);
+  double *T = (double *)malloc(sizeof(double) * (size_t)nx * nv);
+  int rc = (cp && dp && T) ? OR_OK : OR_ENOMEM;
+  for (int j = 0; j < nv && rc == OR_OK; ++j)
+    rc = cyclic_line(nx, F + (size_t)j * nx, 1, T + (size_t)j * nx, 1);
+  if (rc == OR_OK)
+    for (int i = 0; i < nx; ++i)
+      thomas_line(nv, T + i, (size_t)nx, C + i, (size_t)nx, cp, dp);
+  free(cp);
+  free(dp);
+  free(T);
+  return rc;
+}
+
 int or_spline_fit(int nx, int nv, const double *F, double *C) {
   if (nx < 2 || nv < 2) return OR_EINVAL;
   int nmax = nx > nv ? nx : nv;
@@ -342,9 +486,13 @@ int or_spline_fit(int nx, int nv, const double *F, double *C) {
   return OR_OK;
 }
 
-static double Cat(const double *C, int nx, int nv, int i, int j) {
-  if (i < 0) i = -i;                 /* c(-1) = c(1) */
-  if (i > nx - 1) i = 2 * (nx - 1) - i; /* c(n) = c(n-2) */
+static double Cat(const double *C, int nx, int nv, int i, int j, int per) {
+  if (per) {
+    i = ((i % nx) + nx) % nx;          /* periodic x (R23) */
+  } else {
+    if (i < 0) i = -i;                 /* c(-1) = c(1) */
+    if (i > nx - 1) i = 2 * (nx - 1) - i; /* c(n) = c(n-2) */
+  }
   if (j < 0) j = -j;
   if (j > nv - 1) j = 2 * (nv - 1) - j;
   return C[(size_t)j * nx + i];
@@ -360,25 +508,39 @@ static void bspline_weights(double u, double b[4]) {
   b[3] = u3 * sixth;
 }
 
-double or_spline_eval(const double *C, int nx, int nv, double sx, double sv) {
-  if (!(sx >= 0.0 && sx <= (double)(nx - 1) && sv >= 0.0 &&
-        sv <= (double)(nv - 1)))
+static double spline_eval_any(const double *C, int nx, int nv, double sx,
+                              double sv, int per) {
+  if (per) {
+    sx = clamp_periodic(sx, nx);
+    if (!(sv >= 0.0 && sv <= (double)(nv - 1))) return 0.0;
+  } else if (!(sx >= 0.0 && sx <= (double)(nx - 1) && sv >= 0.0 &&
+               sv <= (double)(nv - 1))) {
     return 0.0;
+  }
   int i = (int)floor(sx), j = (int)floor(sv);
-  if (i > nx - 2) i = nx - 2;
+  if (!per && i > nx - 2) i = nx - 2;
   if (j > nv - 2) j = nv - 2;
   double bx[4], bv[4];
   bspline_weights(sx - (double)i, bx);
   bspline_weights(sv - (double)j, bv);
   double f = 0.0;
   for (int b = 0; b < 4; ++b) {
-    double row = bx[0] * Cat(C, nx, nv, i - 1, j - 1 + b);
-    row = fma(bx[1], Cat(C, nx, nv, i, j - 1 + b), row);
-    row = fma(bx[2], Cat(C, nx, nv, i + 1, j - 1 + b), row);
-    row = fma(bx[3], Cat(C, nx, nv, i + 2, j - 1 + b), row);
+    double row = bx[0] * Cat(C, nx, nv, i - 1, j - 1 + b, per);
+    row = fma(bx[1], Cat(C, nx, nv, i, j - 1 + b, per), row);
+    row = fma(bx[2], Cat(C, nx, nv, i + 1, j - 1 + b, per), row);
+    row = fma(bx[3], Cat(C, nx, nv, i + 2, j - 1 + b, per), row);
     f = (b == 0) ? bv[0] * row : fma(bv[b], row, f);
   }
   return f;
+}
+
+double or_spline_eval(const double *C, int nx, int nv, double sx, double sv) {
+  return spline_eval_any(C, nx, nv, sx, sv, 0);
+}
+
+double or_spline_eval_periodic(const double *C, int nx, int nv, double sx,
+                               double sv) {
+  return spline_eval_any(C, nx, nv, sx, sv, 1);
 }
 
 /* Monaghan cubic-spline kernel of section 2.3.2 (support 2). */
@@ -410,7 +572,22 @@ static double recon_transport_site(const or_ctx *c, int i, int j, int brute,
   double Qv = elem_qv(c, e / c->mx) + dqv;
   double sx = (Qx - c->p.x_min) * c->inv_dx - 0.5;
   double sv = (Qv - c->p.v_min) * c->inv_dv - 0.5;
-  return or_int1(c->F, c->nx, c->nv, sx, sv);
+  return int1_eval(c->F, c->nx, c->nv, sx, sv, c->per);
+}
+
+/* Lattice neighbour k of an element column (periodic x, reading R23: the
+ * columns wrap and the wrapped neighbour's Lagrangian position moves by one
+ * period, *shift = -Lx or +Lx).  Returns -1 when there is no neighbour. */
+static int lattice_col(const or_ctx *c, int k, double *shift) {
+  *shift = 0.0;
+  if (k >= 0 && k < c->mx) return k;
+  if (!c->per) return -1;
+  if (k < 0) {
+    *shift = -c->Lx;
+    return k + c->mx;
+  }
+  *shift = c->Lx;
+  return k - c->mx;
 }
 
 /* Remap-time value at site (i, j), section 2.3.2: the W-weighted blend
@@ -431,12 +608,13 @@ static int remap_position(const or_ctx *c, double xP, double vP, double *Qx,
   for (int dl = vlo; dl <= vhi; ++dl) {
     for (int dk = xlo; dk <= xhi; ++dk) {
       if (three && dk != 0 && dl != 0) continue;
-      int k = k0 + dk, l = l0 + dl;
-      if (k < 0 || k >= c->mx || l < 0 || l >= c->mv) continue;
+      double shift;
+      int k = lattice_col(c, k0 + dk, &shift), l = l0 + dl;
+      if (k < 0 || l < 0 || l >= c->mv) continue;
       int m = l * c->mx + k;
       double ex, ev;
       elem_map(c, m, xP, vP, &ex, &ev);
-      double qx = elem_qx(c, k) + ex, qv = elem_qv(c, l) + ev;
+      double qx = (elem_qx(c, k) + shift) + ex, qv = elem_qv(c, l) + ev;
       double d = sqrt(dist2(c, ex, ev));
       double w = or_W(2.0 * d);
       sw += w;
@@ -455,12 +633,13 @@ static int remap_position(const or_ctx *c, double xP, double vP, double *Qx,
 }
 
 static double remap_site(const or_ctx *c, int i, int j) {
-  if (i == 0 || j == 0 || i == c->nx - 1 || j == c->nv - 1) return 0.0;
+  if (j == 0 || j == c->nv - 1) return 0.0;
+  if (!c->per && (i == 0 || i == c->nx - 1)) return 0.0;
   double Qx, Qv;
   if (!remap_position(c, site_x(c, i), site_v(c, j), &Qx, &Qv)) return 0.0;
   double sx = (Qx - c->p.x_min) * c->inv_dx - 0.5;
   double sv = (Qv - c->p.v_min) * c->inv_dv - 0.5;
-  return or_spline_eval(c->C, c->nx, c->nv, sx, sv);
+  return spline_eval_any(c->C, c->nx, c->nv, sx, sv, c->per);
 }
 
 /* Mismatch of the Lagrangian positions predicted at site P by the nearest
@@ -479,11 +658,12 @@ static double emap_site(const or_ctx *c, double xP, double vP) {
   static const int nk[4] = {-1, 1, 0, 0}, nl[4] = {0, 0, -1, 1};
   double worst = 0.0;
   for (int q = 0; q < 4; ++q) {
-    int k = k0 + nk[q], l = l0 + nl[q];
-    if (k < 0 || k >= c->mx || l < 0 || l >= c->mv) continue;
+    double shift;
+    int k = lattice_col(c, k0 + nk[q], &shift), l = l0 + nl[q];
+    if (k < 0 || l < 0 || l >= c->mv) continue;
     double ex, ev;
     if (!elem_map(c, l * c->mx + k, xP, vP, &ex, &ev)) continue;
-    double mx = (elem_qx(c, k) + ex) - qx0;
+    double mx = ((elem_qx(c, k) + shift) + ex) - qx0;
     double mv = (elem_qv(c, l) + ev) - qv0;
     double d = sqrt(dist2(c, mx, mv));
     if (d > worst) worst = d;
@@ -551,6 +731,20 @@ static void column_sums(const or_ctx *c, const double *f, double *S) {
   }
 }
 
+/* Periodic x (reading R23): the force of a mass distribution on a ring
+ * with a uniform background of the same total mass (the neutralising ions
+ * of a plasma, or the mean density removed from a periodic gravitating
+ * system).  B(i) is M_right - M_left of eq. (acccomp) minus the
+ * background's own M_right - M_left at site i, M_tot (2 i + 1) / nx; the
+ * force is G (B(i) - mean B), the mean making the field periodic.  G < 0
+ * repels: a plasma with mean density 1 and G = -1/2 has da/dx = rho - 1,
+ * the electron dynamics with a = -E. */
+static double periodic_B(const or_ctx *c, long i) {
+  double bg = c->Mtot * ((double)(2 * i + 1) / (double)c->nx);
+  double Lm = (i >= 1) ? c->Ml[i - 1] : 0.0;
+  return (bg - c->Ml[i]) - Lm;
+}
+
 /* Cumulative mass M_left(i) = sum_{m <= i} M(m) of section 2.5, taken in
  *  chunks of 64 sites: sequential inside a chunk, the chunk carries added
  * sequentially (reading C9).  M_tot is the last cumulative value (R13). */
@@ -567,6 +761,17 @@ static void cumulative_mass(or_ctx *c, const double *M) {
     carry = carry + p;
   }
   c->Mtot = c->Ml[n - 1];
+  if (c->per) {
+    /* the mean of B(i) (see acc_at), summed in the same 64-site chunks */
+    double tot = 0.0;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      int c1 = c0 + 64 < n ? c0 + 64 : n;
+      double p = 0.0;
+      for (int i = c0; i < c1; ++i) p += periodic_B(c, i);
+      tot = tot + p;
+    }
+    c->Bbar = tot / (double)n;
+  }
 }
 
 static double Ml_at(const or_ctx *c, long i) {
@@ -579,6 +784,10 @@ static double Ml_at(const or_ctx *c, long i) {
  * coupling G in the paper's units (reading R14), extended to every integer
  * (a = +G M_tot left of the grid, -G M_tot right of it). */
 static double acc_at(const or_ctx *c, long i) {
+  if (c->per) {
+    long k = ((i % c->nx) + c->nx) % c->nx;
+    return c->p.G * (periodic_B(c, k) - c->Bbar);
+  }
   return c->p.G * ((c->Mtot - Ml_at(c, i)) - Ml_at(c, i - 1));
 }
 /* Finite-difference gradient and Hessian of section 2.5, the gradient as a
@@ -695,7 +904,9 @@ or_ctx *or_create(const or_params *p) {
       p->nx % p->sx || p->nv % p->sv || !(p->dt > 0.0) ||
       !(p->x_max > p->x_min) || !(p->v_max > p->v_min) || p->n_s < 0 ||
       !(p->beta >= 0.0 && p->beta <= 0.5) || !(p->cdyn >= 0.0) ||
-      (p->cdyn > 0.0 && p->force_mode != OR_FORCE_SELF))
+      (p->cdyn > 0.0 && p->force_mode != OR_FORCE_SELF) ||
+      (p->bc != OR_BC_ISOLATED && p->bc != OR_BC_PERIODIC) ||
+      (p->bc == OR_BC_PERIODIC && p->force_mode != OR_FORCE_SELF))
     return NULL;
   or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
   if (!c) return NULL;
@@ -713,6 +924,8 @@ or_ctx *or_create(const or_params *p) {
   c->dvm = p->sv * c->dv;
   c->rx = 1.0 / c->dxm;
   c->rv = 1.0 / c->dvm;
+  c->per = p->bc == OR_BC_PERIODIC;
+  c->Lx = p->x_max - p->x_min;
   size_t N2 = (size_t)c->nx * c->nv;
   c->F = (double *)calloc(N2, sizeof(double));
   c->C = (double *)calloc(N2, sizeof(double));
@@ -752,10 +965,12 @@ int or_init_conditions(or_ctx *c, const double *f0) {
   for (int j = 0; j < c->nv; ++j)
     for (int i = 0; i < c->nx; ++i) {
       double v = f0[(size_t)j * c->nx + i];
-      if (i == 0 || j == 0 || i == c->nx - 1 || j == c->nv - 1) v = 0.0;
+      if (j == 0 || j == c->nv - 1) v = 0.0;
+      if (!c->per && (i == 0 || i == c->nx - 1)) v = 0.0;
       c->F[(size_t)j * c->nx + i] = v;
     }
-  int rc = or_spline_fit(c->nx, c->nv, c->F, c->C);
+  int rc = c->per ? or_spline_fit_periodic(c->nx, c->nv, c->F, c->C)
+                 : or_spline_fit(c->nx, c->nv, c->F, c->C);
   if (rc) return rc;
   reset_elements(c);
   c->t = 0.0;
@@ -787,7 +1002,8 @@ int or_remap(or_ctx *c) {
   for (int j = 0; j < nv; ++j)
     for (int i = 0; i < nx; ++i) c->f[(size_t)j * nx + i] = remap_site(c, i, j);
   memcpy(c->F, c->f, sizeof(double) * (size_t)nx * nv);
-  rc = or_spline_fit(nx, nv, c->F, c->C);
+  rc = c->per ? or_spline_fit_periodic(nx, nv, c->F, c->C)
+              : or_spline_fit(nx, nv, c->F, c->C);
   if (rc) return rc;
   reset_elements(c);
   return OR_OK;
@@ -958,7 +1174,8 @@ int or_diagnostics(or_ctx *c, double *out7) {
   double epot = 0.0;
   if (c->p.force_mode == OR_FORCE_SELF) {
     if (c->p.G != 0.0) {
-      double GM = c->p.G * c->Mtot;
+      /* periodic: the field energy of the zero-mean force (R23) */
+      double GM = c->per ? 0.0 : c->p.G * c->Mtot;
       for (int i = 0; i < nx; ++i) {
         double a = acc_at(c, i);
         kadd(&pot, a * a - GM * GM);
@@ -1044,7 +1261,8 @@ int or_inverse_map(const double *el12, double dxm, double dvm, double xP,
   double inv = 1.0 / det;
   double dqx, dqv;
   int valid = inv_map(el12[SX_], el12[SV_], tvv * inv, -txv * inv, -tvx * inv,
-                      txx * inv, el12 + HXXX, dxm, dvm, xP, vP, &dqx, &dqv);
+                      txx * inv, el12 + HXXX, dxm, dvm, xP, vP, 0.0, &dqx,
+                      &dqv);
   out4[0] = dqx;
   out4[1] = dqv;
   out4[2] = (double)valid;

@@ -32,6 +32,9 @@ extern "C" {
 #define OR_FORCE_SELF 0
 #define OR_FORCE_EXTERNAL 1
 
+#define OR_BC_ISOLATED 0
+#define OR_BC_PERIODIC 1
+
 #define OR_SCHEME_TRANSPORT 0
 #define OR_SCHEME_REMAP 1
 
@@ -49,6 +52,8 @@ typedef struct or_params {
   int32_t emap_every;  /* steps between E_map checks (adaptive remap) */
   double cdyn;         /* variable step dt <= cdyn / sqrt(rho_max) (<= 0:
                           fixed dt); self-consistent force only */
+  int32_t bc;          /* OR_BC_ISOLATED or OR_BC_PERIODIC (x periodic, force
+                          against a uniform background; self force only) */
 } or_params;
 
 typedef struct or_ctx or_ctx;
@@ -79,8 +84,13 @@ int or_set_threads(int n);
 
 /* primitives, exposed for the pins */
 double or_int1(const double *F, int nx, int nv, double sx, double sv);
+double or_int1_periodic(const double *F, int nx, int nv, double sx,
+                        double sv);
 double or_W(double x);
 int or_spline_fit(int nx, int nv, const double *F, double *C);
+int or_spline_fit_periodic(int nx, int nv, const double *F, double *C);
+double or_spline_eval_periodic(const double *C, int nx, int nv, double sx,
+                               double sv);
 double or_spline_eval(const double *C, int nx, int nv, double sx, double sv);
 int or_inverse_map(const double *el12, double dxm, double dvm, double xP,
                    double vP, double *out4);
