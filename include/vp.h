@@ -68,6 +68,9 @@ extern "C" {
 #define VP_FORCE_SELF 0     /* a = G (M_right - M_left), eq. acccomp */
 #define VP_FORCE_EXTERNAL 1 /* a = a0 + a1 x + a2 x^2 (closed-form tests) */
 
+#define VP_BC_ISOLATED 0 /* isolated system in a fixed box (section 2.5) */
+#define VP_BC_PERIODIC 1 /* x periodic: plasma (G < 0) or periodic gravity */
+
 #define VP_SCHEME_TRANSPORT 0 /* nearest element + six-point interpolation */
 #define VP_SCHEME_REMAP 1     /* W-blended Q_r + cubic B-spline */
 
@@ -101,13 +104,32 @@ typedef struct vp_params {
                           accepted by the serving loop.  Step sizes and t
                           stay on the device (vp_time and vp_diagnostics
                           synchronise to read them). */
+  int32_t bc;          /* VP_BC_ISOLATED, or VP_BC_PERIODIC: x periodic with
+                          period x_max - x_min (the paper notes that its
+                          Poisson solve carries over to periodic systems and
+                          the method to plasmas, section 2.5 and the
+                          conclusions).  The force is that of the ring
+                          against a uniform background of the same mass,
+                          a(i) = G (B(i) - mean B), B(i) = M_tot (2i+1)/nx -
+                          M_left(i) - M_left(i-1): G > 0 gravitating, G < 0
+                          repelling (G = -1/2 with mean density 1 is the
+                          electron plasma, da/dx = rho - 1).  Elements
+                          re-enter the box after each drift and are seen
+                          through their nearest image; F_ini and the spline
+                          repeat in x; only the v edge rows are zeroed.
+                          Requires VP_FORCE_SELF and nx a multiple of 8;
+                          element positions passed to vp_set_elements must
+                          lie in [x_min, x_max).  Not accepted by the
+                          serving loop. */
 } vp_params;
 
 typedef struct vp_diag {
   double mass;        /* dx dv sum f (section 3.2) */
   double e_kin;       /* 1/2 sum v^2 f dx dv */
-  double e_pot;       /* -1/(4G) sum (a^2 - G^2 M_tot^2) dx (self gravity) or
-                         sum phi_ext rho dx (external force) */
+  double e_pot;       /* -1/(4G) sum (a^2 - G^2 M_tot^2) dx (self gravity),
+                         -1/(4G) sum a^2 dx (periodic x: the field energy,
+                         1/2 sum E^2 dx for the plasma) or sum phi_ext rho
+                         dx (external force) */
   double energy;      /* e_kin + e_pot */
   double entropy;     /* Casimir S = -sum f ln|f| dx dv, f != 0 */
   double max_det_dev; /* max over elements of |det T - 1| (eq. detJ) */

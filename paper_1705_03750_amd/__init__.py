@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libvp.so")
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 FORCE_SELF, FORCE_EXTERNAL = 0, 1
+BC_ISOLATED, BC_PERIODIC = 0, 1
 SCHEME_TRANSPORT, SCHEME_REMAP = 0, 1
 BETA_PAPER = 0.5 * (1.0 - math.sqrt(3.0) / 2.0)
 
@@ -46,7 +47,7 @@ class Params(C.Structure):
                 ("ext_a0", C.c_double), ("ext_a1", C.c_double),
                 ("ext_a2", C.c_double), ("precision", C.c_int32),
                 ("emap_max", C.c_double), ("emap_every", C.c_int32),
-                ("c_dyn", C.c_double)]
+                ("c_dyn", C.c_double), ("bc", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -139,7 +140,7 @@ def make_params(nx, nv=None, x_min=-1.0, x_max=1.0, v_min=-1.0, v_max=1.0,
                 sx=8, sv=None, G=1.0, dt=1e-3, n_s=0, beta=BETA_PAPER,
                 force_mode=FORCE_SELF, ext=(0.0, 0.0, 0.0),
                 precision="fp64", emap_max=0.0, emap_every=0,
-                c_dyn=0.0) -> Params:
+                c_dyn=0.0, bc=0) -> Params:
     prec = {"fp64": FP64, "mixed": MIXED}[precision] \
         if isinstance(precision, str) else int(precision)
     nv = nx if nv is None else nv
@@ -148,7 +149,7 @@ def make_params(nx, nv=None, x_min=-1.0, x_max=1.0, v_min=-1.0, v_max=1.0,
                   float(v_max), int(sx), int(sv), float(G), float(dt),
                   int(n_s), float(beta), int(force_mode), float(ext[0]),
                   float(ext[1]), float(ext[2]), prec, float(emap_max),
-                  int(emap_every), float(c_dyn))
+                  int(emap_every), float(c_dyn), int(bc))
 
 
 def footprint(**kw) -> int:
@@ -165,7 +166,7 @@ class VlasovRun:
 
     Keyword parameters follow vp_params (nx, nv, x_min..v_max, sx, sv, G,
     dt, n_s, beta, force_mode, ext=(a0, a1, a2), precision='fp64'|'mixed',
-    emap_max, emap_every, c_dyn).
+    emap_max, emap_every, c_dyn, bc).
     The workspace is one torch uint8 tensor; work is enqueued on the current
     torch stream of `device` (or `stream`, a torch.cuda.Stream)."""
 

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(512) void kb_recon(
     const int bx = local % R.k.nbx, gy = local / R.k.nbx;
     KP p = R.k;
     p.tau = 0.5 * p.dt * pi.h;
-    recon_tile<FT, MODE>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
+    recon_tile<FT, MODE, 0>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
                          R.flags, R.F, R.part, R.fout, nullptr, R.dpart, R.ovf,
                          bx, gy);
   }
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(512) void kb_remap(
     const int bx = local % R.k.nbx, gy = local / R.k.nbx;
     KP p = R.k;
     p.tau = 0.5 * p.dt * pi.h;
-    remap_tile<FT, 0>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
+    remap_tile<FT, 0, 0>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
                       R.flags, R.C, R.F, R.ovf, bx, gy);
   }
 }

@@ -57,7 +57,10 @@ bool params_ok(const vp_params *p) {
          (int64_t)(p->nx / p->sx) * (p->nv / p->sv) <= (1 << 30) &&
          !(p->emap_max > 0.0 && p->emap_every < 1) && !std::isnan(p->emap_max) &&
          p->c_dyn >= 0.0 && std::isfinite(p->c_dyn) &&
-         !(p->c_dyn > 0.0 && p->force_mode != VP_FORCE_SELF);
+         !(p->c_dyn > 0.0 && p->force_mode != VP_FORCE_SELF) &&
+         (p->bc == VP_BC_ISOLATED ||
+          (p->bc == VP_BC_PERIODIC && p->force_mode == VP_FORCE_SELF &&
+           p->nx % 8 == 0));
 }
 
 // list capacity per 8x8 block: about twice the element count whose windows
@@ -109,6 +112,11 @@ KP make_kp(const vp_params *p) {
   k.cdyn = p->c_dyn;
   k.clk = nullptr;  // set by vp_create for a variable step
   k.par = 0;
+  k.per = p->bc == VP_BC_PERIODIC;
+  k.nbl = p->nx / 8;
+  k.x_max = p->x_max;
+  k.Lx = p->x_max - p->x_min;
+  k.hL = 0.5 * k.Lx;
   return k;
 }
 
@@ -148,7 +156,8 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.acc = take((size_t)3 * (k.nx + 8) * 8);
   L.dpart = take((size_t)3 * k.nbx * k.ngy * 8);
   L.dout = take(16 * 8);
-  L.tab = take((size_t)2 * (k.nx + k.nv) * fb);
+  // spline tables: x pivots, v pivots, and (periodic x) z and den
+  L.tab = take((size_t)(3 * k.nx + 2 * k.nv + 1) * fb);
   L.total = o;
   return L;
 }
@@ -330,7 +339,8 @@ template <typename FT, int MODE>
 int launch_recon(vp_ctx *c, void *fout, int *aout, double *rho_out) {
   const KP &k = c->k;
   ProfScope ps(c, PK_RECON);
-  hipLaunchKernelGGL((k_recon<FT, MODE>), dim3(c->L.nwg_x * c->L.nwg_y),
+  auto kern = k.per ? k_recon<FT, MODE, 1> : k_recon<FT, MODE, 0>;
+  hipLaunchKernelGGL(kern, dim3(c->L.nwg_x * c->L.nwg_y),
                      dim3(512), 0, c->stream, k, c->at<double>(c->L.rec),
                      c->at<double>(c->L.qm), c->counts(c->cur),
                      c->at<int>(c->L.lst), c->at<int>(c->L.flags),
@@ -399,21 +409,49 @@ int fit_spline_t(vp_ctx *c) {
   ProfScope ps(c, PK_FIT);
   FT *tab = c->at<FT>(c->L.tab);
   FT *cpx = tab, *rix = tab + k.nx, *cpv = tab + 2 * k.nx,
-     *riv = tab + 2 * k.nx + k.nv;
+     *riv = tab + 2 * k.nx + k.nv, *zx = tab + 2 * k.nx + 2 * k.nv,
+     *den = tab + 3 * k.nx + 2 * k.nv;
   hipLaunchKernelGGL((k_fit_x<FT>), dim3(grid_for(k.nv, FIT_LINES)),
                      dim3(FIT_THREADS), 0,
                      c->stream, k, c->at<FT>(c->L.F), c->at<FT>(c->L.T), cpx,
                      rix);
   VP_LAUNCH_CHECK(c, "k_fit_x");
+  if (k.per) {
+    hipLaunchKernelGGL((k_fit_x_cyclic<FT>), dim3(k.nv), dim3(256), 0,
+                       c->stream, k, c->at<FT>(c->L.T), zx, den);
+    VP_LAUNCH_CHECK(c, "k_fit_x_cyclic");
+  }
   hipLaunchKernelGGL((k_fit_v<FT>), dim3(grid_for(k.nx, FIT_LINES)),
                      dim3(FIT_THREADS), 0,
                      c->stream, k, c->at<FT>(c->L.T), c->at<FT>(c->L.C), cpv,
                      riv);
   VP_LAUNCH_CHECK(c, "k_fit_v");
+  if (k.per) {
+    hipLaunchKernelGGL((k_ghost_periodic<FT>), dim3(grid_for(k.nv + 2, 256)),
+                       dim3(256), 0, c->stream, k, c->at<FT>(c->L.C), -1,
+                       k.nv);
+    VP_LAUNCH_CHECK(c, "k_ghost_periodic");
+    return VP_OK;
+  }
   hipLaunchKernelGGL((k_ghost_x<FT>), dim3(grid_for(k.nv + 2, 256)), dim3(256),
                      0, c->stream, k, c->at<FT>(c->L.C));
   VP_LAUNCH_CHECK(c, "k_ghost_x");
   return VP_OK;
+}
+
+// Periodic x: the ghost columns of F_ini after its interior was written.
+template <typename FT>
+int ghost_F_t(vp_ctx *c) {
+  hipLaunchKernelGGL((k_ghost_periodic<FT>), dim3(grid_for(c->k.nv, 256)),
+                     dim3(256), 0, c->stream, c->k, c->at<FT>(c->L.F), 0,
+                     c->k.nv - 1);
+  VP_LAUNCH_CHECK(c, "k_ghost_periodic");
+  return VP_OK;
+}
+
+int ghost_F(vp_ctx *c) {
+  if (!c->k.per) return VP_OK;
+  return c->mixed() ? ghost_F_t<float>(c) : ghost_F_t<double>(c);
 }
 
 int fit_spline(vp_ctx *c) {
@@ -424,7 +462,8 @@ template <typename FT, int TO_F>
 int launch_remap_t(vp_ctx *c, void *fout) {
   ProfScope ps(c, PK_REMAP);
   FT *out = TO_F ? reinterpret_cast<FT *>(fout) : c->at<FT>(c->L.F);
-  hipLaunchKernelGGL((k_remap_eval<FT, TO_F>),
+  auto kern = c->k.per ? k_remap_eval<FT, TO_F, 1> : k_remap_eval<FT, TO_F, 0>;
+  hipLaunchKernelGGL(kern,
                      dim3(c->L.nwg_x * c->L.nwg_y),
                      dim3(512), 0, c->stream, c->k, c->at<double>(c->L.rec),
                      c->at<double>(c->L.qm), c->counts(c->cur),
@@ -441,6 +480,7 @@ int do_remap(vp_ctx *c) {
   rc = c->mixed() ? launch_remap_t<float, 0>(c, nullptr)
                   : launch_remap_t<double, 0>(c, nullptr);
   if (rc) return rc;
+  if ((rc = ghost_F(c))) return rc;
   if ((rc = fit_spline(c))) return rc;
   c->reset_step = c->step;
   return launch_reset(c);
@@ -542,16 +582,54 @@ void host_tables(int n, std::vector<FT> &cp, std::vector<FT> &ri) {
   }
 }
 
+// Periodic x: Thomas pivots of the tridiagonal part B of the cyclic
+// (1, 4, 1) system (diagonal 8, 4, .., 4, 4.25, unit off-diagonals; the
+// corners go into the Sherman-Morrison term with gamma = -4), the solution
+// z of B z = (-4, 0, .., 0, 1), and den = (1 + z_0) - z_{n-1} / 4.
+template <typename FT>
+void host_tables_cyclic(int n, std::vector<FT> &cp, std::vector<FT> &ri,
+                        std::vector<FT> &z, FT &den) {
+  cp.assign(n, (FT)0);
+  ri.assign(n, (FT)0);
+  z.assign(n, (FT)0);
+  auto diag = [n](int i) {
+    return i == 0 ? (FT)8 : (i == n - 1 ? (FT)4.25 : (FT)4);
+  };
+  FT rinv = (FT)1 / diag(0);
+  ri[0] = rinv;
+  cp[0] = rinv;
+  std::vector<FT> d(n);
+  d[0] = (FT)-4 * rinv;
+  for (int i = 1; i < n; ++i) {
+    const FT dn = diag(i) - cp[i - 1];
+    rinv = (FT)1 / dn;
+    ri[i] = rinv;
+    cp[i] = rinv;
+    const FT u = (i == n - 1) ? (FT)1 : (FT)0;
+    d[i] = (u - d[i - 1]) * rinv;
+  }
+  z[n - 1] = d[n - 1];
+  for (int i = n - 2; i >= 0; --i) z[i] = d[i] - cp[i] * z[i + 1];
+  den = ((FT)1 + z[0]) - (FT)0.25 * z[n - 1];
+}
+
 template <typename FT>
 int upload_tables(vp_ctx *c) {
-  std::vector<FT> cpx, rix, cpv, riv;
-  host_tables<FT>(c->k.nx, cpx, rix);
+  std::vector<FT> cpx, rix, cpv, riv, zx;
+  FT den = (FT)1;
+  if (c->k.per)
+    host_tables_cyclic<FT>(c->k.nx, cpx, rix, zx, den);
+  else
+    host_tables<FT>(c->k.nx, cpx, rix);
   host_tables<FT>(c->k.nv, cpv, riv);
+  zx.resize(c->k.nx, (FT)0);
   std::vector<FT> all;
   all.insert(all.end(), cpx.begin(), cpx.end());
   all.insert(all.end(), rix.begin(), rix.end());
   all.insert(all.end(), cpv.begin(), cpv.end());
   all.insert(all.end(), riv.begin(), riv.end());
+  all.insert(all.end(), zx.begin(), zx.end());
+  all.push_back(den);
   // the host copy lives as long as the context, so no wait is needed
   c->host_tab.assign(reinterpret_cast<const char *>(all.data()),
                      reinterpret_cast<const char *>(all.data() + all.size()));
@@ -738,6 +816,7 @@ int vp_init_conditions(vp_ctx *c, const double *f0, int f0_on_device) {
       if (e != hipSuccess) return dev_fail(c, e, "f0 upload");
     }
   }
+  if ((rc = ghost_F(c))) return rc;
   if ((rc = fit_spline(c))) return rc;
   c->step = 0;
   c->k.par = 0;
@@ -1327,7 +1406,7 @@ int vp_server_run(vp_server *s, const vp_request *reqs, int n,
       int q = -1;
       if (rq.params.precision != s->precision || rq.nsteps < 1 ||
           !rq.f0_dev || !rq.f_out_dev || rq.params.emap_max > 0.0 ||
-          rq.params.c_dyn > 0.0 ||
+          rq.params.c_dyn > 0.0 || rq.params.bc != VP_BC_ISOLATED ||
           vp_footprint(&rq.params, &need) != VP_OK ||
           align_up(need) > s->pool_bytes - header_bytes(s->precision)) {
         res[r].status = VP_EINVAL;

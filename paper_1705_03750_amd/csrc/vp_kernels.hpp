@@ -58,7 +58,45 @@ struct KP {
   double cdyn;
   double *clk;
   int par;  // clock slot of the current step (step count & 1)
+  // Periodic x (the plasma / periodic-gravity variant): period Lx, half
+  // period hL, and nbl = nx / 8 query blocks per row, the first and the
+  // last block column of a row group being one block split by the seam.
+  int per, nbl;
+  double Lx, hL, x_max;
 };
+
+// Periodic x: a position moved out of [x_min, x_max) by a drift re-enters
+// from the other side (one period at most; a sum that rounds onto x_max is
+// put on x_min).
+__device__ __forceinline__ double wrap_x(const KP &p, double x) {
+  if (x < p.x_min) {
+    x = x + p.Lx;
+    if (x >= p.x_max) x = p.x_min;
+  } else if (x >= p.x_max) {
+    x = x - p.Lx;
+    if (x < p.x_min) x = p.x_min;
+  }
+  return x;
+}
+
+// x offset of a site from an element, through the element's nearest image
+// when x is periodic.
+template <int PER>
+__device__ __forceinline__ double image_dx(const KP &p, double d) {
+  if (PER) {
+    if (d > p.hL)
+      d = d - p.Lx;
+    else if (d < -p.hL)
+      d = d + p.Lx;
+  }
+  return d;
+}
+
+// Block column whose list a reconstruction block reads: with periodic x the
+// last column (the right part of the seam block) shares the first one's.
+__device__ __forceinline__ int list_bx(const KP &p, int bx) {
+  return (p.per && bx >= p.nbl) ? bx - p.nbl : bx;
+}
 
 // Device clock of a variable-step run: two slots of {dt, t, t_r, tau}, the
 // slot of step n holding the step size and start time of step n, the time
@@ -174,6 +212,7 @@ __device__ __forceinline__ void elem_store(double *__restrict__ st, size_t E,
 
 __device__ __forceinline__ void elem_drift(const KP &p, ElemState &s) {
   s.x = fma(p.h, s.v, s.x);
+  if (p.per) s.x = wrap_x(p, s.x);
   s.txx = fma(p.h, s.tvx, s.txx);
   s.txv = fma(p.h, s.tvv, s.txv);
   s.hx0 = fma(p.h, s.hv0, s.hx0);
@@ -238,7 +277,8 @@ __device__ __forceinline__ void elem_kick(const KP &p, const Acc &acc,
 __device__ __forceinline__ bool block_meets_window(
     const KP &p, double X, double V, double axx, double axv, double avx,
     double avv, int i0, int j0) {
-  const int ia = max(0, i0), ib = min(p.nx - 1, i0 + 7);
+  // periodic x: i0 is an unwrapped column near the element, all 8 live
+  const int ia = p.per ? i0 : max(0, i0), ib = p.per ? i0 + 7 : min(p.nx - 1, i0 + 7);
   const int ja = max(0, j0), jb = min(p.nv - 1, j0 + 7);
   const double xa = site_x(p, ia), xb = site_x(p, ib);
   const double va = site_v(p, ja), vb = site_v(p, jb);
@@ -299,10 +339,28 @@ __device__ __forceinline__ void elem_record(
   if (!reg) return;
   const double cx = (s.x - p.x_min) * p.inv_dx - 0.5;
   const double cv = (s.v - p.v_min) * p.inv_dv - 0.5;
-  const double xlo = fmax(cx - rxs, -1.0), xhi = fmin(cx + rxs, (double)p.nx);
   const double vlo = fmax(cv - rvs, -1.0), vhi = fmin(cv + rvs, (double)p.nv);
-  const int ilo = max(0, (int)ceil(xlo)), ihi = min(p.nx - 1, (int)floor(xhi));
   const int jlo = max(0, (int)ceil(vlo)), jhi = min(p.nv - 1, (int)floor(vhi));
+  int ilo, ihi;
+  if (p.per) {
+    // unwrapped columns around the element (cx in [-0.5, nx - 0.5)); a
+    // window reaching half the period, or spanning more block columns than
+    // a row has, is too wide for the nearest-image lists
+    if (!(rxs < 0.5 * (double)p.nx - 2.0)) {
+      atomicOr(flags, FLAG_WIDE);
+      return;
+    }
+    ilo = (int)ceil(cx - rxs);
+    ihi = (int)floor(cx + rxs);
+    if (ihi - ilo > p.nx - 24) {
+      atomicOr(flags, FLAG_WIDE);
+      return;
+    }
+  } else {
+    const double xlo = fmax(cx - rxs, -1.0), xhi = fmin(cx + rxs, (double)p.nx);
+    ilo = max(0, (int)ceil(xlo));
+    ihi = min(p.nx - 1, (int)floor(xhi));
+  }
   if (ilo > ihi || jlo > jhi) return;
   const int b0v = blk(jlo, p.ov, p.obv), b1v = blk(jhi, p.ov, p.obv);
   // blocks per row of the window's box, whatever the row group's x offset
@@ -331,7 +389,8 @@ __device__ __forceinline__ void elem_record(
         const int i0 = o + 8 * (bxq - 1), j0 = p.ov + 8 * (bvq - p.obv);
         if (bxq <= blk(ihi, o, 1) &&
             block_meets_window(p, s.x, s.v, axx, axv, avx, avv, i0, j0))
-          bb[k] = bvq * p.nbx + bxq;
+          bb[k] = bvq * p.nbx +
+                  (p.per ? ((bxq % p.nbl) + p.nbl) % p.nbl : bxq);
       }
       slot[k] = (bb[k] >= 0) ? atomicAdd(&cnt[bb[k]], 1) : p.cap;
     }
@@ -434,12 +493,12 @@ __global__ __launch_bounds__(256) void k_fill(T *__restrict__ a, long long n,
 // the record, dQ = l + A u' with u'_c = l^T (-H_c/2) l, which equals
 // l - A u / 2 bit for bit (scaling by a power of two commutes with every
 // rounding step).
-template <typename R>
+template <int PER, typename R>
 __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
                                                 double xP, double vP,
                                                 double &bd, int &best,
                                                 double &bdqx, double &bdqv) {
-  const double dx = xP - r[R_X], dv = vP - r[R_V];
+  const double dx = image_dx<PER>(p, xP - r[R_X]), dv = vP - r[R_V];
   const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
   const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
   if (fabs(lx) < p.dxm && fabs(lv) < p.dvm) {
@@ -460,11 +519,12 @@ __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
 }
 
 // Same map without the validity test (neighbour predictions at remap).
+template <int PER>
 __device__ __forceinline__ void element_map(const KP &p,
                                             const double *__restrict__ r,
                                             double xP, double vP, double &dqx,
                                             double &dqv) {
-  const double dx = xP - r[R_X], dv = vP - r[R_V];
+  const double dx = image_dx<PER>(p, xP - r[R_X]), dv = vP - r[R_V];
   const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
   const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
   const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
@@ -475,14 +535,15 @@ __device__ __forceinline__ void element_map(const KP &p,
 }
 
 // The map with its validity (the neighbour predictions of E_map).
+template <int PER>
 __device__ __forceinline__ bool element_map_valid(const KP &p,
                                                   const double *__restrict__ r,
                                                   double xP, double vP,
                                                   double &dqx, double &dqv) {
-  const double dx = xP - r[R_X], dv = vP - r[R_V];
+  const double dx = image_dx<PER>(p, xP - r[R_X]), dv = vP - r[R_V];
   const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
   const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
-  element_map(p, r, xP, vP, dqx, dqv);
+  element_map<PER>(p, r, xP, vP, dqx, dqv);
   return fabs(lx) < p.dxm && fabs(lv) < p.dvm;
 }
 
@@ -518,6 +579,7 @@ __device__ __forceinline__ int list_head(const KP &p, const int *L) {
 // each; the candidate loop then reads them as uniform LDS broadcasts.
 // L is the block's list row, id0 its first entries (lane-indexed, loaded by
 // the caller together with the count n).
+template <int PER>
 __device__ __forceinline__ int query_block(
     const KP &p, const double *__restrict__ rec, const int *__restrict__ L,
     int id0, int n, bool scan_all, double xP, double vP, double &dqx,
@@ -557,7 +619,7 @@ __device__ __forceinline__ int query_block(
         Rec r;
 #pragma unroll
         for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
-        query_candidate(p, r, e, xP, vP, bd, best, dqx, dqv);
+        query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -567,7 +629,7 @@ __device__ __forceinline__ int query_block(
     for (int e = 0; e < p.E; ++e) {
       Rec r;
       load_rec(rec, e, r);
-      query_candidate(p, r, e, xP, vP, bd, best, dqx, dqv);
+      query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
     }
   }
   return best;
@@ -575,14 +637,24 @@ __device__ __forceinline__ int query_block(
 
 // ------------------------------------------------------- interpolations
 
+// Periodic x: interpolation positions are clamped to [-12, nx + 11] sites
+// (16 ghost columns of periodic copies hold every stencil point; only an
+// element far outside its validity could reach beyond).
+__device__ __forceinline__ double clamp_periodic(const KP &p, double sx) {
+  if (sx < -12.0) return -12.0;
+  if (sx > (double)p.nx + 11.0) return (double)p.nx + 11.0;
+  return sx;
+}
+
 // Six-point second-order interpolation (section 2.2.1, eq. int1 with the
 // Lagrange signs) of F at index-space position (sx, sv).  F points at the
 // grid origin of a zero-padded array.
 template <typename FT>
 __device__ __forceinline__ FT int1(const KP &p, const FT *__restrict__ F,
                                    double sx, double sv) {
+  if (p.per) sx = clamp_periodic(p, sx);
   const double fin = floor(sx + 0.5), fjn = floor(sv + 0.5);
-  if (!(fin >= -1.0 && fin <= (double)p.nx && fjn >= -1.0 &&
+  if (!((p.per || (fin >= -1.0 && fin <= (double)p.nx)) && fjn >= -1.0 &&
         fjn <= (double)p.nv))
     return (FT)0;
   const double fic = floor(sx), fjc = floor(sv);
@@ -624,11 +696,12 @@ __device__ __forceinline__ void bspline_w(double ud, FT b[4]) {
 template <typename FT>
 __device__ __forceinline__ FT spline_eval(const KP &p, const FT *__restrict__ C,
                                           double sx, double sv) {
-  if (!(sx >= 0.0 && sx <= (double)(p.nx - 1) && sv >= 0.0 &&
+  if (p.per) sx = clamp_periodic(p, sx);
+  if (!((p.per || (sx >= 0.0 && sx <= (double)(p.nx - 1))) && sv >= 0.0 &&
         sv <= (double)(p.nv - 1)))
     return (FT)0;
   int i = (int)floor(sx), j = (int)floor(sv);
-  if (i > p.nx - 2) i = p.nx - 2;
+  if (!p.per && i > p.nx - 2) i = p.nx - 2;
   if (j > p.nv - 2) j = p.nv - 2;
   FT bx[4], bv[4];
   bspline_w<FT>(sx - (double)i, bx);
@@ -725,6 +798,78 @@ __device__ __forceinline__ double ld_coherent(const double *q) {
       __HIP_MEMORY_SCOPE_AGENT));
 }
 
+// Periodic x: M_right - M_left of eq. (acccomp) at site k in [0, nx)
+// minus the uniform background's own, M_tot (2 k + 1) / nx.
+__device__ __forceinline__ double periodic_B(const KP &p, const double *M,
+                                             double Mtot, int k) {
+  const double bg = Mtot * ((double)(2 * k + 1) / (double)p.nx);
+  const double Lm = (k >= 1) ? M[k - 1] : 0.0;
+  return (bg - M[k]) - Lm;
+}
+
+// Mean of B over the ring, summed in the 64-site chunks of M_left (NT
+// threads, the whole workgroup; sc holds nch + 1 LDS doubles, free again
+// on return).
+template <int NT>
+__device__ __forceinline__ double periodic_mean(const KP &p, const double *M,
+                                                double Mtot, double *sc) {
+  const int nx = p.nx, tid = threadIdx.x;
+  const int nch = (nx + MCHUNK - 1) / MCHUNK;
+  for (int c = tid; c < nch; c += NT) {
+    const int i1 = min(c * MCHUNK + MCHUNK, nx);
+    double t = 0.0;
+    for (int i = c * MCHUNK; i < i1; ++i) t += periodic_B(p, M, Mtot, i);
+    sc[c] = t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int c = 0; c < nch; ++c) t = t + sc[c];
+    sc[nch] = t / (double)nx;
+  }
+  __syncthreads();
+  const double r = sc[nch];
+  __syncthreads();
+  return r;
+}
+
+// a at any integer site i from M_left: eq. (acccomp) (constant beyond the
+// grid), or with periodic x the force against the background, G (B - mean
+// B) at i mod nx.
+__device__ __forceinline__ double acc_site(const KP &p, const double *M,
+                                           double Mtot, double Bbar, int i) {
+  if (p.per) {
+    const int k = ((i % p.nx) + p.nx) % p.nx;
+    return p.G * (periodic_B(p, M, Mtot, k) - Bbar);
+  }
+  return p.G * ((Mtot - Ml_at(M, p.nx, Mtot, i)) - Ml_at(M, p.nx, Mtot, i - 1));
+}
+
+// a, a', a'' at table index q (site i = q - 4) from M_left: a' as a centred
+// difference over 2 dx, a'' the three-point second difference.
+__device__ __forceinline__ void acc_from_mass(const KP &p, const double *M,
+                                              double Mtot, double Bbar, int q,
+                                              double &a0, double &da,
+                                              double &d2a) {
+  const int i = q - 4;
+  const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
+  const double am = acc_site(p, M, Mtot, Bbar, i - 1);
+  a0 = acc_site(p, M, Mtot, Bbar, i);
+  const double ap = acc_site(p, M, Mtot, Bbar, i + 1);
+  da = (ap - am) / two_dx;
+  d2a = ((ap + am) - 2.0 * a0) / dx2;
+}
+
+struct AccFromMass {
+  const KP &p;
+  const double *M;
+  double Mtot, Bbar;
+  __device__ __forceinline__ void at(int q, double &a, double &da,
+                                     double &d2a) const {
+    acc_from_mass(p, M, Mtot, Bbar, q, a, da, d2a);
+  }
+};
+
 // Largest value over the 64 lanes of a wavefront (order-free: max is exact).
 __device__ __forceinline__ double wave_max(double m) {
 #pragma unroll
@@ -735,7 +880,7 @@ __device__ __forceinline__ double wave_max(double m) {
 // LDS of one field workgroup
 struct FieldLds {
   double stage[FIELD_WG];
-  double car[FIELD_CHUNKS];
+  double car[FIELD_CHUNKS + 1];
   double red[FIELD_WG / 64];
   int last;
 };
@@ -820,18 +965,13 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
   __syncthreads();
   const double *Ml = A.Ml;
   const double Mtot = Ml[nx - 1];
+  const double Bbar =
+      p.per ? periodic_mean<FIELD_WG>(p, Ml, Mtot, L.car) : 0.0;
   const int n8 = nx + 8;
-  const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
   for (int q = tid; q < n8; q += FIELD_WG) {
     const int i = q - 4;
-    const double am = p.G * ((Mtot - Ml_at(Ml, nx, Mtot, i - 1)) -
-                             Ml_at(Ml, nx, Mtot, i - 2));
-    const double a0 = p.G * ((Mtot - Ml_at(Ml, nx, Mtot, i)) -
-                             Ml_at(Ml, nx, Mtot, i - 1));
-    const double ap = p.G * ((Mtot - Ml_at(Ml, nx, Mtot, i + 1)) -
-                             Ml_at(Ml, nx, Mtot, i));
-    const double da = (ap - am) / two_dx;
-    const double d2a = ((ap + am) - 2.0 * a0) / dx2;
+    double a0, da, d2a;
+    acc_from_mass(p, Ml, Mtot, Bbar, q, a0, da, d2a);
     A.acc[q] = a0;
     A.acc[n8 + q] = da;
     A.acc[2 * n8 + q] = d2a;
@@ -944,46 +1084,21 @@ __device__ __forceinline__ double mass_to_lds(const KP &p, const double *in,
   return M[nx - 1];
 }
 
-// a, a', a'' at table index q (site i = q - 4) from M_left: the operations
-// of the field kernels' force loop.
-__device__ __forceinline__ void acc_from_mass(const KP &p, const double *M,
-                                              double Mtot, int q, double &a0,
-                                              double &da, double &d2a) {
-  const int nx = p.nx, i = q - 4;
-  const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
-  const double am = p.G * ((Mtot - Ml_at(M, nx, Mtot, i - 1)) -
-                           Ml_at(M, nx, Mtot, i - 2));
-  a0 = p.G * ((Mtot - Ml_at(M, nx, Mtot, i)) - Ml_at(M, nx, Mtot, i - 1));
-  const double ap = p.G * ((Mtot - Ml_at(M, nx, Mtot, i + 1)) -
-                           Ml_at(M, nx, Mtot, i));
-  da = (ap - am) / two_dx;
-  d2a = ((ap + am) - 2.0 * a0) / dx2;
-}
-
-struct AccFromMass {
-  const KP &p;
-  const double *M;
-  double Mtot;
-  __device__ __forceinline__ void at(int q, double &a, double &da,
-                                     double &d2a) const {
-    acc_from_mass(p, M, Mtot, q, a, da, d2a);
-  }
-};
-
 __global__ __launch_bounds__(1024) void k_field1(KP p, FieldArgs A) {
   __shared__ double M[FIELD1_MAX];
-  __shared__ double car[FIELD1_MAX / MCHUNK];
+  __shared__ double car[FIELD1_MAX / MCHUNK + 1];
   __shared__ double red[1024 / 64];
   const int nx = p.nx, tid = threadIdx.x;
   double rmax = 0.0;
   const double Mtot = mass_to_lds<1024>(p, A.in, A.ngy, A.in_is_rho,
                                         A.rho_out, M, car, red, rmax);
+  const double Bbar = p.per ? periodic_mean<1024>(p, M, Mtot, car) : 0.0;
   if (p.clk && tid == 0) p.clk[CK_RHO] = rmax;
   for (int i = tid; i < nx; i += 1024) A.Ml[i] = M[i];
   const int n8 = nx + 8;
   for (int q = tid; q < n8; q += 1024) {
     double a0, da, d2a;
-    acc_from_mass(p, M, Mtot, q, a0, da, d2a);
+    acc_from_mass(p, M, Mtot, Bbar, q, a0, da, d2a);
     A.acc[q] = a0;
     A.acc[n8 + q] = da;
     A.acc[2 * n8 + q] = d2a;
@@ -1035,7 +1150,7 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
     int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
     int predict, int reg) {
   __shared__ double M[FIELD1_MAX];
-  __shared__ double car[FIELD1_MAX / MCHUNK];
+  __shared__ double car[FIELD1_MAX / MCHUNK + 1];
   __shared__ double red[ELEMF_WG / 64];
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long gsz = (long long)gridDim.x * blockDim.x;
@@ -1047,9 +1162,10 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
   double rmax = 0.0;
   const double Mtot = mass_to_lds<ELEMF_WG>(p, part, p.ngy, 0, nullptr, M,
                                             car, red, rmax);
+  const double Bbar = p.per ? periodic_mean<ELEMF_WG>(p, M, Mtot, car) : 0.0;
   const double dtn = elem_clock(p, rmax, predict, gid == 0);
   if (e >= p.E) return;
-  elem_kick(p, AccFromMass{p, M, Mtot}, s);
+  elem_kick(p, AccFromMass{p, M, Mtot, Bbar}, s);
   if (predict) {
     p.h = 0.5 * dtn;
     elem_drift(p, s);
@@ -1080,7 +1196,7 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
     int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
     int predict, int reg) {
   __shared__ double M[FIELD1_MAX];
-  __shared__ double car[FIELD1_MAX / MCHUNK];
+  __shared__ double car[FIELD1_MAX / MCHUNK + 1];
   __shared__ int s_ok;
   __shared__ double s_rmax;
   const int tid = threadIdx.x, nx = p.nx;
@@ -1166,11 +1282,12 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
   __syncthreads();
   for (int i = tid; i < nx; i += ELEMC_WG) M[i] = car[i / MCHUNK] + M[i];
   __syncthreads();
+  const double Mtot = M[nx - 1];
+  const double Bbar = p.per ? periodic_mean<ELEMC_WG>(p, M, Mtot, car) : 0.0;
   if (!s_ok) return;
   const double dtn = elem_clock(p, p.clk ? s_rmax : 0.0, predict, gid == 0);
   if (e >= p.E) return;
-  const double Mtot = M[nx - 1];
-  elem_kick(p, AccFromMass{p, M, Mtot}, s);
+  elem_kick(p, AccFromMass{p, M, Mtot, Bbar}, s);
   if (predict) {
     p.h = 0.5 * dtn;
     elem_drift(p, s);
@@ -1181,6 +1298,21 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
 
 // ------------------------------------------------------- reconstruction
 
+// Lattice neighbour column k of an element (k may be -1 or mx): -1 when
+// there is none; with periodic x the columns wrap and the wrapped
+// neighbour's Lagrangian position moves by one period (shift).
+__device__ __forceinline__ int lattice_col(const KP &p, int k, double &shift) {
+  shift = 0.0;
+  if (k >= 0 && k < p.mx) return k;
+  if (!p.per) return -1;
+  if (k < 0) {
+    shift = -p.Lx;
+    return k + p.mx;
+  }
+  shift = p.Lx;
+  return k - p.mx;
+}
+
 // One workgroup = 8 wavefronts stacked in v; one wavefront = one 8x8-site
 // query block (lane -> site: x = lane & 7, v = lane >> 3).  The workgroup
 // covers 8 columns x 64 rows, the row group of the fixed column-sum order.
@@ -1189,7 +1321,7 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
 // partials of its row group (the strips in order); the field adds the
 // groups in increasing order.  No workgroup waits on another, so the
 // launch needs no device-scope synchronisation.
-template <typename FT, int MODE>
+template <typename FT, int MODE, int PER>
 __device__ __forceinline__ void recon_tile(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
     const int *__restrict__ cnt,
@@ -1211,7 +1343,7 @@ __device__ __forceinline__ void recon_tile(
   double f = 0.0, em = 0.0;
   int best = -1;
   if (blk_ok) {
-    const int b = bv * p.nbx + bx;
+    const int b = bv * p.nbx + list_bx(p, bx);
     const int *L = lst + (size_t)b * p.cap;
     const int id0 = list_head(p, L);
     const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
@@ -1219,8 +1351,8 @@ __device__ __forceinline__ void recon_tile(
     if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
     const double xP = site_x(p, i), vP = site_v(p, j);
     double dqx, dqv;
-    best = query_block(p, rec, L, id0, n, scan_all, xP, vP, dqx, dqv,
-                       qstage[w]);
+    best = query_block<PER>(p, rec, L, id0, n, scan_all, xP, vP, dqx, dqv,
+                            qstage[w]);
     if (live && best >= 0) {
       const double Qx = qm[2 * (size_t)best] + dqx;
       const double Qv = qm[2 * (size_t)best + 1] + dqv;
@@ -1243,12 +1375,13 @@ __device__ __forceinline__ void recon_tile(
       const int nk[4] = {-1, 1, 0, 0}, nl[4] = {0, 0, -1, 1};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int k = k0 + nk[q], l = l0 + nl[q];
-        if (k < 0 || k >= p.mx || l < 0 || l >= p.mv) continue;
+        double shift;
+        const int k = lattice_col(p, k0 + nk[q], shift), l = l0 + nl[q];
+        if (k < 0 || l < 0 || l >= p.mv) continue;
         const size_t m = (size_t)l * p.mx + k;
         double ex, ev;
-        if (!element_map_valid(p, rec + m * RS, xP, vP, ex, ev)) continue;
-        const double mx = (qm[2 * m] + ex) - qx0;
+        if (!element_map_valid<PER>(p, rec + m * RS, xP, vP, ex, ev)) continue;
+        const double mx = ((qm[2 * m] + shift) + ex) - qx0;
         const double mv = (qm[2 * m + 1] + ev) - qv0;
         const double zx = mx * p.rx, zv = mv * p.rv;
         em = fmax(em, sqrt(fma(zx, zx, zv * zv)));
@@ -1307,7 +1440,7 @@ __device__ __forceinline__ void recon_tile(
   }
 }
 
-template <typename FT, int MODE>
+template <typename FT, int MODE, int PER>
 __global__ __launch_bounds__(512) void k_recon(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
     const int *__restrict__ cnt,
@@ -1317,8 +1450,8 @@ __global__ __launch_bounds__(512) void k_recon(
     unsigned long long *__restrict__ ovf) {
   const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
   clock_tau(p);
-  recon_tile<FT, MODE>(p, rec, qm, cnt, lst, flags, F, part, fout, aout, dpart,
-                       ovf, t % p.nbx, t / p.nbx);
+  recon_tile<FT, MODE, PER>(p, rec, qm, cnt, lst, flags, F, part, fout, aout,
+                            dpart, ovf, t % p.nbx, t / p.nbx);
 }
 
 // Resampling value at every site (section 2.3.2): nearest element, the
@@ -1326,7 +1459,7 @@ __global__ __launch_bounds__(512) void k_recon(
 // values), W(2d)-weighted blend of their predictions Q_r, cubic B-spline of
 // F_ini at Q_r; the outermost ring is zero.  Writes F (padded interior)
 // when TO_F == 0, else f_out.
-template <typename FT, int TO_F>
+template <typename FT, int TO_F, int PER>
 __device__ __forceinline__ void remap_tile(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
     const int *__restrict__ cnt,
@@ -1341,7 +1474,7 @@ __device__ __forceinline__ void remap_tile(
   const int i = group_ox(p, gy) + 8 * (bx - 1) + (lane & 7);
   const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
   const bool live = i >= 0 && i < p.nx && j >= 0 && j < p.nv;
-  const int b = bv * p.nbx + bx;
+  const int b = bv * p.nbx + list_bx(p, bx);
   const int *L = lst + (size_t)b * p.cap;
   const int id0 = list_head(p, L);
   const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
@@ -1349,11 +1482,13 @@ __device__ __forceinline__ void remap_tile(
   if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
   const double xP = site_x(p, i), vP = site_v(p, j);
   double dqx, dqv;
-  const int best = query_block(p, rec, L, id0, n, scan_all, xP, vP, dqx, dqv,
-                               qstage[w]);
+  const int best = query_block<PER>(p, rec, L, id0, n, scan_all, xP, vP, dqx,
+                                    dqv, qstage[w]);
   if (!live) return;
   FT val = (FT)0;
-  const bool ring = (i == 0 || j == 0 || i == p.nx - 1 || j == p.nv - 1);
+  // zero edge rows (and columns, unless x is periodic)
+  const bool ring = (j == 0 || j == p.nv - 1) ||
+                    (!PER && (i == 0 || i == p.nx - 1));
   if (!ring && best >= 0) {
     const int l0 = best / p.mx, k0 = best - l0 * p.mx;
     const double zx = dqx * p.rx, zv = dqv * p.rv, beta = p.beta;
@@ -1364,12 +1499,13 @@ __device__ __forceinline__ void remap_tile(
     for (int dl = vlo; dl <= vhi; ++dl) {
       for (int dk = xlo; dk <= xhi; ++dk) {
         if (three && dk != 0 && dl != 0) continue;
-        const int k = k0 + dk, l = l0 + dl;
-        if (k < 0 || k >= p.mx || l < 0 || l >= p.mv) continue;
+        double shift;
+        const int k = lattice_col(p, k0 + dk, shift), l = l0 + dl;
+        if (k < 0 || l < 0 || l >= p.mv) continue;
         const size_t m = (size_t)(l * p.mx + k);
         double ex, ev;
-        element_map(p, rec + m * RS, xP, vP, ex, ev);
-        const double qx = qm[2 * m] + ex, qv = qm[2 * m + 1] + ev;
+        element_map<PER>(p, rec + m * RS, xP, vP, ex, ev);
+        const double qx = (qm[2 * m] + shift) + ex, qv = qm[2 * m + 1] + ev;
         const double ax = ex * p.rx, av = ev * p.rv;
         const double d = sqrt(fma(ax, ax, av * av));
         const double wt = W_kernel(2.0 * d);
@@ -1397,7 +1533,7 @@ __device__ __forceinline__ void remap_tile(
     Fout[(size_t)j * p.nx + i] = val;
 }
 
-template <typename FT, int TO_F>
+template <typename FT, int TO_F, int PER>
 __global__ __launch_bounds__(512) void k_remap_eval(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
     const int *__restrict__ cnt,
@@ -1406,8 +1542,8 @@ __global__ __launch_bounds__(512) void k_remap_eval(
     unsigned long long *__restrict__ ovf) {
   const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
   clock_tau(p);
-  remap_tile<FT, TO_F>(p, rec, qm, cnt, lst, flags, C, Fout, ovf, t % p.nbx,
-                       t / p.nbx);
+  remap_tile<FT, TO_F, PER>(p, rec, qm, cnt, lst, flags, C, Fout, ovf,
+                            t % p.nbx, t / p.nbx);
 }
 
 // Diagnostics (section 3.2): sums of the per-workgroup partials, potential
@@ -1428,7 +1564,8 @@ __global__ __launch_bounds__(1024) void k_diag(
   const double Mtot = Ml[p.nx - 1];
   const int n8 = p.nx + 8;
   if (p.force_mode == 0) {
-    const double GM = p.G * Mtot;
+    // periodic x: the field energy of the zero-mean force alone
+    const double GM = p.per ? 0.0 : p.G * Mtot;
     for (int i = tid; i < p.nx; i += blockDim.x) {
       const double a = acc[i + 4];
       pot += a * a - GM * GM;
@@ -1520,6 +1657,7 @@ struct FitLine {
   const FT *coef;  // 1/den (forward) or cp (backward), per position
   int n;           // positions
   int nl;          // lines of this workgroup (<= 64)
+  int last2;       // the last row's sub-diagonal is 2 (mirror end), else 1
 };
 
 template <typename FT>
@@ -1687,7 +1825,7 @@ __device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
           for (int u = 0; u < 16; ++u) col[(k0 + u) * LP] = v[u];
         }
         for (int k = kb; k < kn; ++k) {
-          const FT sd = (i0 + k == n - 1) ? (FT)2 * acc : acc;
+          const FT sd = (G.last2 && i0 + k == n - 1) ? (FT)2 * acc : acc;
           acc = ((FT)6 * col[k * LP] - sd) * cf[k];
           col[k * LP] = acc;
         }
@@ -1762,6 +1900,7 @@ __device__ __forceinline__ void fit_x_rows(const KP &p, const FT *__restrict__ F
   G.out_ls = p.nx;
   G.out_ps = 1;
   G.coef = rix;
+  G.last2 = !p.per;  // periodic x: the cyclic system's tridiagonal part
   fit_sweep<FT, false, false, false>(G, S);
   G.in = G.out;
   G.in_ls = G.out_ls;
@@ -1788,6 +1927,7 @@ __device__ __forceinline__ void fit_v_cols(const KP &p, const FT *__restrict__ T
   G.out_ls = 1;
   G.out_ps = p.pitch;
   G.coef = riv;
+  G.last2 = 1;
   fit_sweep<FT, true, false, false>(G, S);
   G.in = G.out;
   G.in_ps = G.out_ps;
@@ -1829,6 +1969,37 @@ __global__ __launch_bounds__(256) void k_ghost_x(KP p, FT *__restrict__ C) {
   ghost_x_rows<FT>(p, C, blockIdx.x);
 }
 
+// Periodic x, cyclic spline system (Sherman-Morrison): T holds y = B^-1 6F
+// per row (B the tridiagonal part, diagonal 8, 4, .., 4, 4.25); with z =
+// B^-1 (-4, 0, .., 0, 1) the coefficients are y - [(y_0 - y_{n-1}/4) / den]
+// z, den = (1 + z_0) - z_{n-1}/4.  One workgroup per row.
+template <typename FT>
+__global__ __launch_bounds__(256) void k_fit_x_cyclic(
+    KP p, FT *__restrict__ T, const FT *__restrict__ z,
+    const FT *__restrict__ den) {
+  FT *row = T + (size_t)blockIdx.x * p.nx;
+  const FT num = row[0] - (FT)0.25 * row[p.nx - 1];
+  const FT fact = num / den[0];
+  __syncthreads();  // every thread has read y_0 and y_{n-1}
+  for (int i = threadIdx.x; i < p.nx; i += 256) row[i] = row[i] - fact * z[i];
+}
+
+// Periodic x: 16 ghost columns on each side of rows [jlo, jhi] hold copies
+// of the other end of the row (one thread per row).
+template <typename FT>
+__global__ __launch_bounds__(256) void k_ghost_periodic(KP p,
+                                                        FT *__restrict__ A,
+                                                        int jlo, int jhi) {
+  const int j = jlo + (int)(blockIdx.x * 256 + threadIdx.x);
+  if (j > jhi) return;
+  FT *row = A + (long)(j + PV) * p.pitch + PX;
+#pragma unroll 4
+  for (int k = 1; k <= PX; ++k) {
+    row[-k] = row[p.nx - k];
+    row[p.nx - 1 + k] = row[k - 1];
+  }
+}
+
 
 // Rows [j0, j0 + nrows) of f0 (double, src holds those rows) -> F (padded
 // interior), the outermost ring zeroed.
@@ -1843,7 +2014,8 @@ __global__ __launch_bounds__(256) void k_load_f0(KP p,
        q += gsz) {
     const int jr = (int)(q / p.nx), i = (int)(q - (long long)jr * p.nx);
     const int j = j0 + jr;
-    const bool ring = (i == 0 || j == 0 || i == p.nx - 1 || j == p.nv - 1);
+    const bool ring = (j == 0 || j == p.nv - 1) ||
+                      (!p.per && (i == 0 || i == p.nx - 1));
     F[(long)(j + PV) * p.pitch + (i + PX)] = ring ? (FT)0 : (FT)src[q];
   }
 }

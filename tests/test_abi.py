@@ -48,7 +48,10 @@ def test_footprint_and_validation(vp):
                 dict(nx=64, sx=4, dt=1e-3, c_dyn=-0.5),
                 dict(nx=64, sx=4, dt=1e-3, c_dyn=float("inf")),
                 # the variable step needs the self-consistent density
-                dict(nx=64, sx=4, dt=1e-3, c_dyn=0.1, force_mode=1)):
+                dict(nx=64, sx=4, dt=1e-3, c_dyn=0.1, force_mode=1),
+                dict(nx=36, sx=4, dt=1e-3, bc=1),   # periodic: nx % 8
+                dict(nx=64, sx=4, dt=1e-3, bc=1, force_mode=1),
+                dict(nx=64, sx=4, dt=1e-3, bc=2)):
         with pytest.raises(vp.VPError) as ei:
             vp.footprint(**bad)
         assert ei.value.code == vp.EINVAL

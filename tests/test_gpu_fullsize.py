@@ -88,6 +88,24 @@ def test_c2_full_size_mixed(vp, orc):
     g.sync()
 
 
+def test_p2_plasma_full_size(vp, orc):
+    """2048^2 periodic plasma (two-stream workload), FP64: 10 steps, a
+    resampling, 2 more; elements bitwise, f and rho to 1e-12."""
+    cfg, f0 = W.config("p2_two_stream_2048")
+    o, g = run_pair(vp, orc, cfg, f0)
+    print(f"[p2 fp64] n={cfg.n} s={cfg.s}", flush=True)
+    o.step(10)
+    g.step(10)
+    o.remap()
+    g.remap()
+    o.step(2)
+    g.step(2)
+    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    assert rel_linf(g.density().cpu().numpy(), o.density()) <= RTOL
+    g.sync()
+
+
 @pytest.mark.timeout(400)
 @pytest.mark.parametrize("name,steps", [("c3_halos_sheet_8192", 2),
                                         ("c5_halos_cold_16384", 1)])

@@ -25,7 +25,7 @@ import numpy as np
 
 __all__ = [
     "RunConfig", "site_coords", "finish", "gaussian_blob", "halo_sum",
-    "spitzer_sheet", "config", "CONFIGS", "serving_requests",
+    "spitzer_sheet", "two_stream", "config", "CONFIGS", "serving_requests",
 ]
 
 
@@ -41,12 +41,13 @@ class RunConfig:
     G: float = 1.0
     box: tuple = (-1.0, 1.0, -1.0, 1.0)
     seed: int = 0
+    bc: int = 0            # 1: x periodic (plasma / periodic gravity)
 
     def params(self, precision: str = "fp64") -> dict:
         x0, x1, v0, v1 = self.box
         return dict(nx=self.n, nv=self.n, x_min=x0, x_max=x1, v_min=v0,
                     v_max=v1, sx=self.s, sv=self.s, G=self.G, dt=self.dt,
-                    n_s=self.n_s, precision=precision)
+                    n_s=self.n_s, precision=precision, bc=self.bc)
 
 
 def site_coords(n: int, lo: float, hi: float) -> np.ndarray:
@@ -140,6 +141,14 @@ CONFIGS = {
                                steps=2000, n_s=50, seed=2),
     "c3_halos_sheet_8192": RunConfig("c3_halos_sheet_8192", n=8192, s=8,
                                      dt=2.5e-4, steps=4000, n_s=50, seed=3),
+    # electron plasma on a ring (x periodic, G = -1/2, mean density 1):
+    # two counter-streaming Maxwellian beams (v = +-2.4, unit dispersion)
+    # with a 1 % density perturbation of wavenumber 0.2 -- the two-stream
+    # instability, whose phase-space vortices wind the elements up
+    "p2_two_stream_2048": RunConfig("p2_two_stream_2048", n=2048, s=8,
+                                    dt=0.05, steps=2000, n_s=50, G=-0.5,
+                                    box=(0.0, 10.0 * math.pi, -8.0, 8.0),
+                                    seed=7, bc=1),
     "c5_halos_cold_16384": RunConfig("c5_halos_cold_16384", n=16384, s=16,
                                      dt=1.25e-4, steps=1000, n_s=20, seed=5),
 }
@@ -167,9 +176,26 @@ def config(name: str, n: int | None = None) -> tuple[RunConfig, np.ndarray]:
     elif name.startswith("c5"):
         f = halo_sum(nx, nv, box, rng, 8, mass=0.8)
         f += 0.2 * _unit_gaussian(nx, nv, box, 0.0, 0.0, 0.2, 0.02)
+    elif name.startswith("p2"):
+        return cfg, two_stream(nx, nv, box, 0.2, 2.4, 0.01)
     else:
         raise KeyError(name)
     return cfg, finish(f, box, 1.0)
+
+
+def two_stream(nx: int, nv: int, box, k: float, v0: float,
+               alpha: float) -> np.ndarray:
+    """(1 + alpha cos(k x)) [N(v0, 1) + N(-v0, 1)] / 2 on a periodic box
+    (no x edge ring: x wraps); the v edge rows are zeroed and the mean
+    density over the box is 1."""
+    x = site_coords(nx, box[0], box[1])
+    v = site_coords(nv, box[2], box[3])
+    X, V = np.meshgrid(x, v)
+    beams = 0.5 * (np.exp(-0.5 * (V - v0) ** 2) + np.exp(-0.5 * (V + v0) ** 2))
+    f = (1.0 + alpha * np.cos(k * X)) * beams / math.sqrt(2.0 * math.pi)
+    f[0, :] = 0.0
+    f[-1, :] = 0.0
+    return f
 
 
 def serving_requests(count: int = 512, base_seed: int = 4000,
