@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vp_oracle.c")
+_SRC4 = os.path.join(_HERE, "vp4_oracle.c")
 _OUTDIR = os.path.join(_HERE, "_build")
 _LIB_PATH = os.path.join(_OUTDIR, "liboracle.so")
 
@@ -36,7 +37,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(_OUTDIR, exist_ok=True)
     tmp = _LIB_PATH + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-fopenmp", "-Wall", "-o", tmp, _SRC, "-lm"]
+           "-fPIC", "-shared", "-fopenmp", "-Wall", "-o", tmp, _SRC, _SRC4,
+           "-lm"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + res.stderr)
