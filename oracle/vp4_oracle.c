@@ -667,15 +667,23 @@ static double remap_site(const or4_ctx *c, long long q) {
 
 /* ----------------------------------------------------------------- field */
 
-/* rho(i, j) = du dw sum_{l, k} f, l outer, k inner. */
+/* rho(i, j) = du dw sum over the velocity sites (u, w), in a fixed order
+ * (reading R24, like C9 in 2D): 4 x 4 velocity blocks, w-block outer and
+ * u-block inner, each block's 16 values summed w outer, u inner, and the
+ * block sums added in that order. */
 static void density(const or4_ctx *c, const double *f, double *rho) {
-  int ns = c->ns, nv = c->nv;
+  int ns = c->ns, nv = c->nv, nb = nv / 4;
   for (int j = 0; j < ns; ++j)
     for (int i = 0; i < ns; ++i) {
       double s = 0.0;
-      for (int l = 0; l < nv; ++l)
-        for (int k = 0; k < nv; ++k)
-          s += f[(((size_t)l * nv + k) * ns + j) * ns + i];
+      for (int bw = 0; bw < nb; ++bw)
+        for (int bu = 0; bu < nb; ++bu) {
+          double part = 0.0;
+          for (int l = 4 * bw; l < 4 * bw + 4; ++l)
+            for (int k = 4 * bu; k < 4 * bu + 4; ++k)
+              part += f[(((size_t)l * nv + k) * ns + j) * ns + i];
+          s += part;
+        }
       rho[(size_t)j * ns + i] = (c->du * c->du) * s;
     }
 }
@@ -874,7 +882,7 @@ static void kick_and_correct(or4_ctx *c, double dt) {
 /* -------------------------------------------------------------- public */
 
 or4_ctx *or4_create(const or4_params *p) {
-  if (!p || p->ns < 8 || p->nv < 4 || p->ss < 1 || p->sv < 1 ||
+  if (!p || p->ns < 8 || p->nv < 4 || p->nv % 4 || p->ss < 1 || p->sv < 1 ||
       p->ns % p->ss || p->nv % p->sv || !(p->dt > 0.0) || !(p->L > 0.0) ||
       !(p->vmax > 0.0) || p->n_s < 0 || !(p->beta >= 0.0 && p->beta <= 0.5))
     return NULL;

@@ -15,6 +15,8 @@ SRC = os.path.join(HERE, "csrc", "vp_engine.hip")
 DEPS = [SRC, os.path.join(HERE, "csrc", "vp_kernels.hpp"),
         os.path.join(ROOT, "include", "vp.h")]
 LIB = os.path.join(HERE, "libvp.so")
+SRC4 = os.path.join(HERE, "csrc", "vp4_engine.hip")
+LIB4 = os.path.join(HERE, "libvp4.so")
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -33,19 +35,26 @@ def flags() -> list[str]:
             "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
-    """Compile libvp.so (always rebuilds; atomic replace of the output)."""
+def _compile(src: str, out: str, verbose: bool, extra=()) -> str:
     tmp = out + ".tmp"
-    cmd = [hipcc()] + flags() + list(extra) + ["-o", tmp, SRC]
+    cmd = [hipcc()] + flags() + list(extra) + ["-o", tmp, src]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("libvp build failed:\n" + res.stderr[-6000:])
+        raise RuntimeError(f"{os.path.basename(out)} build failed:\n" +
+                           res.stderr[-6000:])
     if verbose:
         print(" ".join(cmd))
         if res.stderr:
             print(res.stderr[-3000:])
     os.replace(tmp, out)
     return out
+
+
+def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+    """Compile libvp.so (the 2D phase-space engine) and libvp4.so (the 4D
+    one); always rebuilds, atomic replace of the outputs."""
+    _compile(SRC4, LIB4, verbose, extra)
+    return _compile(SRC, out, verbose, extra)
 
 
 if __name__ == "__main__":

@@ -68,3 +68,27 @@ def test_create_rejects_small_or_null_workspace(vp):
     assert vp.lib().vp_create(C.byref(p), C.c_void_p(256), n.value - 1, None,
                               C.byref(h)) == vp.ENOMEM
     assert b"vp_footprint" in vp.lib().vp_last_error(None)
+
+
+def test_vp4_exports_and_validation():
+    """The 4D library loads (no GPU needed), exports every symbol its
+    header declares, and validates parameters."""
+    import ctypes as C
+    import re
+    import paper_1705_03750_amd.vp4 as v4
+    L = v4.lib()
+    hdr = open(os.path.join(ROOT, "include", "vp4.h")).read()
+    declared = set(re.findall(r"\b(vp4_[a-z_]+)\s*\(", hdr))
+    assert declared == set(v4.EXPORTS)
+    for name in declared:
+        getattr(L, name)
+    n = C.c_size_t(0)
+    ok = v4.make_params(ns=16, nv=8, L=1.0, vmax=1.0, ss=4, sv=4)
+    assert L.vp4_footprint(C.byref(ok), C.byref(n)) == 0 and n.value > 0
+    for bad in (dict(ns=18, nv=8, L=1.0, vmax=1.0, ss=2, sv=4),
+                dict(ns=16, nv=6, L=1.0, vmax=1.0, ss=4, sv=2),
+                dict(ns=16, nv=8, L=0.0, vmax=1.0, ss=4, sv=4),
+                dict(ns=16, nv=8, L=1.0, vmax=1.0, ss=4, sv=4, precision=3)):
+        p = v4.make_params(**bad)
+        assert L.vp4_footprint(C.byref(p), C.byref(n)) == v4.VP4Error(
+            -1, "").code
