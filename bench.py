@@ -156,6 +156,66 @@ def periodic_leg(steps: int, warmup: int):
                                     for k, v in r["kernels"].items() if v[1]}}
 
 
+# 4D reconstruction: one full candidate evaluation (l = A dP 28, u = l^T H l
+# 140, dQ 48, d^2 10 FP64 flops) for each of the 2^4 windows holding a site
+FLOPS_PER_EVAL_4D = 226
+EVALS_PER_SITE_4D = 16
+
+
+def four_d_leg(steps: int = 20):
+    """The 4D phase-space engine (2D periodic space x 2D velocity): a
+    Maxwellian plasma with seeded low-mode perturbations on 64^4 sites,
+    elements every 4th site per axis, dt 0.1, resampling every 10 steps,
+    mixed precision.  Times the run from t = 0 (plain pass), then the
+    per-kernel durations with HIP events (second pass)."""
+    import torch
+    import paper_1705_03750_amd.vp4 as v4
+    import workloads as W
+    ns = nv = 64
+    L, vmax = 4.0 * math.pi, 6.0
+    f0 = torch.as_tensor(W.landau4(ns, nv, L, vmax, 0.05, seed=1),
+                         device="cuda:0")
+    g = v4.VlasovRun4(device="cuda:0", ns=ns, nv=nv, L=L, vmax=vmax, ss=4,
+                      sv=4, G=-0.5, dt=0.1, n_s=10, precision="mixed")
+    g.init_conditions(f0)
+    g.step(2)
+    out = {}
+    for prof in (False, True):
+        g.init_conditions(f0)
+        g.sync()
+        torch.cuda.synchronize()
+        if prof:
+            g.prof_begin(2 * steps + 8)
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if prof:
+            kern = g.prof_end()
+        else:
+            secs = t1 - t0
+    n4 = ns * ns * nv * nv
+    ms, n = kern["recon"]
+    avg_s = ms / n / 1e3
+    flops = FLOPS_PER_EVAL_4D * EVALS_PER_SITE_4D * n4
+    achieved = flops / avg_s / 1e12
+    d = g.diagnostics()
+    g.close()
+    return {"workload": "q4_landau_64: 64^4 sites, x, y periodic on [0, 4 pi), "
+                        "u, w on [-6, 6), G = -1/2, elements every 4th site, "
+                        "dt 0.1, resampling every 10 steps, mixed precision",
+            "value": n4 * steps / secs, "unit": "site updates/s",
+            "ms_per_step": 1e3 * secs / steps, "steps": steps,
+            "recon_avg_launch_us": avg_s * 1e6,
+            "recon_roofline": {"bound": "alu", "achieved": achieved,
+                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": achieved / FP64_PEAK_TFLOPS,
+                               "algorithmic_flops_per_launch": flops},
+            "kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()
+                                    if v[1]},
+            "mass": d["mass"], "energy": d["energy"]}
+
+
 def cpu_baseline(cfg, f0, steps: int, threads: int):
     import oracle
     used = oracle.set_threads(threads)
@@ -361,6 +421,10 @@ def main():
         out["periodic"] = periodic_leg(args.steps, args.warmup)
         print(f"[bench] periodic plasma: "
               f"{out['periodic']['ms_per_step']:.4f} ms/step",
+              file=sys.stderr, flush=True)
+    if args.only is None:
+        out["four_d"] = four_d_leg()
+        print(f"[bench] 4D: {out['four_d']['ms_per_step']:.3f} ms/step",
               file=sys.stderr, flush=True)
     if not args.no_serve and args.only is None:
         out["serving"] = serve_leg(args.serve_requests, args.serve_step_scale,

@@ -25,7 +25,7 @@ import numpy as np
 
 __all__ = [
     "RunConfig", "site_coords", "finish", "gaussian_blob", "halo_sum",
-    "spitzer_sheet", "two_stream", "config", "CONFIGS", "serving_requests",
+    "spitzer_sheet", "two_stream", "landau4", "config", "CONFIGS", "serving_requests",
 ]
 
 
@@ -181,6 +181,28 @@ def config(name: str, n: int | None = None) -> tuple[RunConfig, np.ndarray]:
     else:
         raise KeyError(name)
     return cfg, finish(f, box, 1.0)
+
+
+def landau4(ns: int, nv: int, L: float, vmax: float, alpha: float,
+            seed: int = 0) -> np.ndarray:
+    """4D phase space (x, y periodic on [0, L), u, w on [-vmax, vmax)): a
+    Maxwellian plasma of mean density 1 with seeded perturbations of the
+    four lowest Fourier modes (1, 0), (0, 1), (1, 1), (1, -1); array
+    (w, u, y, x), the u and w edge rows zero."""
+    rng = np.random.default_rng(seed)
+    x = site_coords(ns, 0.0, L)
+    u = site_coords(nv, -vmax, vmax)
+    W_, U_, Y_, X_ = np.meshgrid(u, u, x, x, indexing="ij")
+    pert = np.ones_like(X_)
+    for mx, my in ((1, 0), (0, 1), (1, 1), (1, -1)):
+        pert += alpha * rng.uniform(0.5, 1.0) * np.cos(
+            2.0 * math.pi * (mx * X_ + my * Y_) / L + rng.uniform(0, 2 * math.pi))
+    f = pert * np.exp(-0.5 * (U_ ** 2 + W_ ** 2)) / (2.0 * math.pi)
+    f[0] = 0.0
+    f[-1] = 0.0
+    f[:, 0] = 0.0
+    f[:, -1] = 0.0
+    return f
 
 
 def two_stream(nx: int, nv: int, box, k: float, v0: float,
