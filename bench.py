@@ -329,7 +329,15 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (5x), "
                          "the reference for scaling rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE counters to bytes")
+    ap.add_argument("--leg", choices=["periodic", "four_d"], default=None,
+                    help="run only this extra leg (for profiling) and print "
+                         "its JSON")
     args = ap.parse_args()
+    if args.leg and args.gpus == 1:
+        res = (periodic_leg(args.steps, args.warmup) if args.leg == "periodic"
+               else four_d_leg(args.steps))
+        print(json.dumps(res))
+        return
     if args.copy_cal:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")

@@ -22,7 +22,7 @@ thread_local std::string g_err4;
 struct Layout {
   size_t F, C, fs, st, rec, cnt, lst, flags, part, rho, re, im, ar, ai, tr, ti,
       fld, tw, tabs, tabv, dpart, dout, total;
-  long long nb;
+  long long nb, nl;  // query blocks, lists
 };
 
 constexpr int NDIAG = 256;  // workgroups of the diagnostic partial sums
@@ -59,8 +59,13 @@ KP make_kp(const vp4_params *p) {
   k.ms = p->ns / p->ss;
   k.mv = p->nv / p->sv;
   k.E = k.ms * k.ms * k.mv * k.mv;
-  k.nbs = p->ns / BLK;
-  k.nbv = p->nv / BLK;
+  for (int a = 0; a < 4; ++a) {
+    const int sp = a < 2 ? p->ss : p->sv, n = a < 2 ? p->ns : p->nv;
+    k.o[a] = (sp / 2) % BLK;
+    k.ob[a] = k.o[a] > 0;
+    k.nb[a] = (n - 1 - k.o[a]) / BLK + k.ob[a] + 1;
+  }
+  k.nls = p->ns / BLK;
   k.cap = list_cap(p->ss, p->sv);
   k.L = p->L;
   k.hL = 0.5 * p->L;
@@ -84,7 +89,8 @@ Layout make_layout(const vp4_params *p, const KP &k) {
   Layout L{};
   const size_t fb = p->precision == VP4_MIXED ? 4 : 8;
   const size_t N4 = (size_t)k.ns * k.ns * k.nv * k.nv, n2 = (size_t)k.ns * k.ns;
-  L.nb = (long long)k.nbs * k.nbs * k.nbv * k.nbv;
+  L.nb = (long long)k.nb[0] * k.nb[1] * k.nb[2] * k.nb[3];
+  L.nl = (long long)k.nls * k.nls * k.nb[2] * k.nb[3];
   size_t o = 0;
   auto take = [&](size_t b) {
     const size_t at = o;
@@ -96,10 +102,10 @@ Layout make_layout(const vp4_params *p, const KP &k) {
   L.fs = take(N4 * fb);
   L.st = take((size_t)NST * k.E * 8);
   L.rec = take((size_t)RS * k.E * 8);
-  L.cnt = take((size_t)L.nb * 4);
-  L.lst = take((size_t)L.nb * k.cap * 4);
+  L.cnt = take((size_t)L.nl * 4);
+  L.lst = take((size_t)L.nl * k.cap * 4);
   L.flags = take(64);
-  L.part = take((size_t)k.nbv * k.nbv * n2 * 8);
+  L.part = take((size_t)k.nb[2] * k.nb[3] * n2 * 8);
   L.rho = take(n2 * 8);
   L.re = take(n2 * 8);
   L.im = take(n2 * 8);
@@ -180,12 +186,14 @@ unsigned grid_for(long long n, int bs) {
 }
 
 int zero_counts(vp4_ctx *c) {
-  hipLaunchKernelGGL(k4_zero, dim3(grid_for(std::min<long long>(c->L.nb, 1 << 22), 256)),
-                     dim3(256), 0, c->stream, c->at<int>(c->L.cnt), c->L.nb);
+  hipLaunchKernelGGL(k4_zero, dim3(grid_for(std::min<long long>(c->L.nl, 1 << 22), 256)),
+                     dim3(256), 0, c->stream, c->at<int>(c->L.cnt), c->L.nl);
   VP4_CHECK(c, "k4_zero");
   return VP4_OK;
 }
 
+// Records and block lists for the current elements (after the predictor's
+// half drift when `drift`).
 int predict(vp4_ctx *c, int drift) {
   int rc;
   if ((rc = zero_counts(c))) return rc;

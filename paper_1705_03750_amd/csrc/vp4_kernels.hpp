@@ -13,10 +13,14 @@
 //   state    SoA [60][E]; rec AoS [E][60]: X (4), A = T^-1 (16), H (40).
 //   lists    per query block of 4^4 sites: a count and cap element ids;
 //            every element whose validity window can reach a site of the
-//            block is listed (x and y wrap).
-//   part     density partials [nbv^2][ns^2] (one row of partial sums per
-//            velocity block); rho [ns^2]; spectra and the 12 force fields
-//            (a_x, a_y, grad a, Hessian of a) [12][ns^2].
+//            block is listed.  Block boundaries sit half an element spacing
+//            (mod 4) off the grid origin, on the element lattice, so that an
+//            undeformed lattice puts 2 elements per axis in each list; the
+//            first and last block of an axis may be partial, and on x and y
+//            they are the two halves of the seam block, which share a list.
+//   part     density partials [velocity blocks][ns^2] (one row of partial
+//            sums per velocity block); rho [ns^2]; spectra and the 12 force
+//            fields (a_x, a_y, grad a, Hessian of a) [12][ns^2].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,7 +43,10 @@ __device__ __constant__ const int PC[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 
 struct KP {
   int ns, nv, ss, sv, ms, mv, E;
-  int nbs, nbv;  // query blocks per space / velocity axis
+  int o[4];      // block origin offset per axis, (spacing / 2) mod 4
+  int ob[4];     // 1 when o > 0 (a partial first block)
+  int nb[4];     // blocks per axis
+  int nls;       // list columns per space axis (ns / 4)
   int cap;       // list slots per block
   double L, hL, vmax, dx, du, inv_dx, inv_du, G, dt, h, beta;
   double Dm[4], rD[4];
@@ -76,6 +83,25 @@ __device__ __forceinline__ double image(const KP &p, double d) {
   return d;
 }
 
+// Query-block geometry: block b of axis a starts at site o_a + 4 (b - ob_a),
+// o_a = (element spacing / 2) mod 4, the element lattice's offset.
+__device__ __forceinline__ int floordiv4(int i) {
+  return (i >= 0) ? i / BLK : -((-i + BLK - 1) / BLK);
+}
+__device__ __forceinline__ int blk_of(const KP &p, int a, int i) {
+  return floordiv4(i - p.o[a]) + p.ob[a];
+}
+__device__ __forceinline__ int blk_first(const KP &p, int a, int b) {
+  return p.o[a] + BLK * (b - p.ob[a]);
+}
+// List of block (bx, by, bu, bw): x and y wrap onto ns / 4 list columns.
+__device__ __forceinline__ long long list_of(const KP &p, int bx, int by, int bu,
+                                             int bw) {
+  const int lx = ((bx % p.nls) + p.nls) % p.nls;
+  const int ly = ((by % p.nls) + p.nls) % p.nls;
+  return (((long long)bw * p.nb[2] + bu) * p.nls + ly) * p.nls + lx;
+}
+
 // ------------------------------------------------------------- elements
 
 __global__ __launch_bounds__(256) void k4_reset(KP p, double *__restrict__ st) {
@@ -102,6 +128,7 @@ __global__ __launch_bounds__(256) void k4_zero(int *__restrict__ a, long long n)
 // x_i += h v_i (then the periodic wrap), T_i. += h T_{i+2}., H_i.. += h
 // H_{i+2}...
 __device__ __forceinline__ void drift4(const KP &p, double *s, double h) {
+#pragma unroll
   for (int i = 0; i < 2; ++i) {
     s[S_P + i] = wrapL(p, fma(h, s[S_P + i + 2], s[S_P + i]));
 #pragma unroll
@@ -151,15 +178,15 @@ __device__ __forceinline__ bool inv4(const double *m, double *r, double &det) {
 }
 
 // Can the validity window of the element (record r) hold a site of the
-// block whose first sites are g0[4] (space columns unwrapped)?  l = A dP is
+// block whose sites span [g0, g1] per axis (space columns unwrapped)?  l = A dP is
 // linear, so over the block's box each l_a ranges over its centre value +-
 // sum_b |A_ab| half-width_b; rounding margins as in the 2D engine.
 __device__ __forceinline__ bool block_meets(const KP &p, const double *r,
-                                            const int g0[4]) {
+                                            const int g0[4], const int g1[4]) {
   double m[4], h[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const double lo = coord(p, a, g0[a]), hi = coord(p, a, g0[a] + BLK - 1);
+    const double lo = coord(p, a, g0[a]), hi = coord(p, a, g1[a]);
     m[a] = 0.5 * (lo + hi) - r[a];
     h[a] = 0.5 * (hi - lo);
   }
@@ -190,20 +217,24 @@ __global__ __launch_bounds__(256) void k4_predict(
   if (e >= p.E) return;
   const size_t E = (size_t)p.E;
   double s[NST];
-#pragma unroll 4
+#pragma unroll
   for (int q = 0; q < NST; ++q) s[q] = st[q * E + e];
   if (drift) {
     drift4(p, s, p.h);
-    for (int q = 0; q < 20; ++q) st[q * E + e] = s[q];
-    for (int q = 20; q < 40; ++q) st[q * E + e] = s[q];
+#pragma unroll
+    for (int q = 0; q < 40; ++q) st[q * E + e] = s[q];
   }
   double A[16], det;
   const bool ok = inv4(s + S_T, A, det);
   double *r = rec + (size_t)e * RS;
+#pragma unroll
   for (int a = 0; a < 4; ++a) r[a] = s[S_P + a];
+#pragma unroll
   for (int q = 0; q < 16; ++q) r[4 + q] = ok ? A[q] : 0.0;
+#pragma unroll
   for (int q = 0; q < 40; ++q) r[20 + q] = s[S_H + q];
   bool bad = !ok;
+#pragma unroll
   for (int a = 0; a < 4; ++a) bad = bad || !isfinite(s[S_P + a]);
   if (bad) {
     atomicOr(flags, FL_NUMERIC);
@@ -213,9 +244,10 @@ __global__ __launch_bounds__(256) void k4_predict(
   // Eulerian reach per axis: |dP_a| <= sum_b |T_ab| Dm_b, in sites, with
   // a relative margin for the rounding of l = A dP
   int blo[4], bhi[4];
-  long long nblk = 1;
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
     double reach = 0.0, tsum = 0.0;
+#pragma unroll
     for (int b = 0; b < 4; ++b) {
       reach = fma(fabs(s[S_T + 4 * a + b]), p.Dm[b], reach);
       tsum += fabs(s[S_T + 4 * a + b]);
@@ -229,47 +261,49 @@ __global__ __launch_bounds__(256) void k4_predict(
       lo = max(lo, 0);
       hi = min(hi, p.nv - 1);
       if (lo > hi) return;
-    } else if (!(rs < 0.5 * (double)p.ns - 2.0 * BLK)) {
+    } else if (!(rs < 0.5 * (double)p.ns - 2.0 * BLK) ||
+               hi - lo > p.ns - 3 * BLK) {
       atomicOr(flags, FL_WIDE);  // too wide for nearest-image lists
       return;
     }
-    // floor division by BLK (lo may be negative on the periodic axes)
-    blo[a] = (lo >= 0) ? lo / BLK : -((-lo + BLK - 1) / BLK);
-    bhi[a] = (hi >= 0) ? hi / BLK : -((-hi + BLK - 1) / BLK);
-    nblk *= (long long)(bhi[a] - blo[a] + 1);
+    blo[a] = blk_of(p, a, lo);  // unwrapped on x and y
+    bhi[a] = blk_of(p, a, hi);
   }
+  const long long nblk = (long long)(bhi[0] - blo[0] + 1) *
+                         (bhi[1] - blo[1] + 1) * (bhi[2] - blo[2] + 1) *
+                         (bhi[3] - blo[3] + 1);
   if (nblk > SPAN) {
     atomicOr(flags, FL_WIDE);
     return;
   }
-  const int nx = bhi[0] - blo[0] + 1, ny = bhi[1] - blo[1] + 1,
-            nu = bhi[2] - blo[2] + 1;
-  for (int q = 0; q < (int)nblk; ++q) {
-    int b[4];
-    int t = q;
-    b[0] = blo[0] + t % nx;
-    t /= nx;
-    b[1] = blo[1] + t % ny;
-    t /= ny;
-    b[2] = blo[2] + t % nu;
-    b[3] = blo[3] + t / nu;
-    const int g0[4] = {BLK * b[0], BLK * b[1], BLK * b[2], BLK * b[3]};
-    if (!block_meets(p, r, g0)) continue;
-    const int bx = ((b[0] % p.nbs) + p.nbs) % p.nbs;
-    const int by = ((b[1] % p.nbs) + p.nbs) % p.nbs;
-    const long long blk =
-        (((long long)b[3] * p.nbv + b[2]) * p.nbs + by) * p.nbs + bx;
-    const int slot = atomicAdd(&cnt[blk], 1);
-    if (slot < p.cap) lst[blk * p.cap + slot] = e;
-  }
+  int b[4], g0[4], g1[4];
+  for (b[3] = blo[3]; b[3] <= bhi[3]; ++b[3])
+    for (b[2] = blo[2]; b[2] <= bhi[2]; ++b[2])
+      for (b[1] = blo[1]; b[1] <= bhi[1]; ++b[1])
+        for (b[0] = blo[0]; b[0] <= bhi[0]; ++b[0]) {
+          for (int a = 0; a < 4; ++a) {
+            g0[a] = blk_first(p, a, b[a]);
+            g1[a] = g0[a] + BLK - 1;
+            if (a >= 2) {  // the live sites of a partial velocity block
+              g0[a] = max(g0[a], 0);
+              g1[a] = min(g1[a], p.nv - 1);
+            }
+          }
+          if (!block_meets(p, r, g0, g1)) continue;
+          const long long blk = list_of(p, b[0], b[1], b[2], b[3]);
+          const int slot = atomicAdd(&cnt[blk], 1);
+          if (slot < p.cap) lst[blk * p.cap + slot] = e;
+        }
 }
 
-// Second-order inverse map of one element (record r) at site P: l = A dP
-// (nearest image in x, y), validity |l_a| < Dm_a, u_a = l^T H_a l over the
-// symmetric pairs, dQ = l - A u / 2.
-__device__ __forceinline__ bool map4(const KP &p, const double *r,
-                                     const double P[4], double dq[4]) {
-  double d[4], l[4], u[4];
+// Second-order inverse map of one element (record r) at site P, in two
+// parts: l = A dP (nearest image in x, y) with the validity |l_a| < Dm_a,
+// then u_a = l^T H_a l over the symmetric pairs and dQ = l - A u / 2.  The
+// query evaluates the second part only where the first found the element
+// valid, so a wavefront skips it for an element valid at none of its sites.
+__device__ __forceinline__ bool map4_l(const KP &p, const double *r,
+                                       const double P[4], double l[4]) {
+  double d[4];
   d[0] = image(p, P[0] - r[0]);
   d[1] = image(p, P[1] - r[1]);
   d[2] = P[2] - r[2];
@@ -281,6 +315,12 @@ __device__ __forceinline__ bool map4(const KP &p, const double *r,
     l[a] = fma(A[3], d[3], fma(A[2], d[2], fma(A[1], d[1], A[0] * d[0])));
     valid = valid && (fabs(l[a]) < p.Dm[a]);
   }
+  return valid;
+}
+
+__device__ __forceinline__ void map4_q(const double *r, const double l[4],
+                                       double dq[4]) {
+  double u[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const double *H = r + 20 + 10 * a;
@@ -304,6 +344,13 @@ __device__ __forceinline__ bool map4(const KP &p, const double *r,
     for (int b = 0; b < 4; ++b) s = fma(-0.5 * A[b], u[b], s);
     dq[a] = s;
   }
+}
+
+__device__ __forceinline__ bool map4(const KP &p, const double *r,
+                                     const double P[4], double dq[4]) {
+  double l[4];
+  const bool valid = map4_l(p, r, P, l);
+  map4_q(r, l, dq);
   return valid;
 }
 
@@ -313,22 +360,28 @@ __device__ __forceinline__ double dist2(const KP &p, const double dq[4]) {
   return fma(z3, z3, fma(z2, z2, fma(z1, z1, z0 * z0)));
 }
 
-// Site of thread t of block blk: (i, j, k, l) and its coordinates.
-__device__ __forceinline__ void block_site(const KP &p, long long blk, int t,
-                                           int g[4], double P[4]) {
+// Site of thread t of block blk (blocks numbered x fastest): (i, j, k, l),
+// its coordinates, whether it lies on the grid, and the block's list.
+__device__ __forceinline__ bool block_site(const KP &p, long long blk, int t,
+                                           int g[4], double P[4], int bb[4],
+                                           long long &list) {
   long long b = blk;
-  const int bx = (int)(b % p.nbs);
-  b /= p.nbs;
-  const int by = (int)(b % p.nbs);
-  b /= p.nbs;
-  const int bu = (int)(b % p.nbv);
-  const int bw = (int)(b / p.nbv);
-  g[0] = BLK * bx + (t & 3);
-  g[1] = BLK * by + ((t >> 2) & 3);
-  g[2] = BLK * bu + ((t >> 4) & 3);
-  g[3] = BLK * bw + (t >> 6);
+  bb[0] = (int)(b % p.nb[0]);
+  b /= p.nb[0];
+  bb[1] = (int)(b % p.nb[1]);
+  b /= p.nb[1];
+  bb[2] = (int)(b % p.nb[2]);
+  bb[3] = (int)(b / p.nb[2]);
+  const int loc[4] = {t & 3, (t >> 2) & 3, (t >> 4) & 3, t >> 6};
+  bool live = true;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) P[a] = coord(p, a, g[a]);
+  for (int a = 0; a < 4; ++a) {
+    g[a] = blk_first(p, a, bb[a]) + loc[a];
+    P[a] = coord(p, a, g[a]);
+    live = live && g[a] >= 0 && g[a] < (a < 2 ? p.ns : p.nv);
+  }
+  list = list_of(p, bb[0], bb[1], bb[2], bb[3]);
+  return live;
 }
 
 // Nearest valid element (smallest (d^2, id)) of the workgroup's block: the
@@ -354,13 +407,17 @@ __device__ __forceinline__ int query4(const KP &p, const double *__restrict__ re
     __syncthreads();
     for (int k = 0; k < m; ++k) {
       const int e = scan_all ? c0 + k : L[c0 + k];
-      double dq[4];
-      if (!map4(p, stage + k * RS, P, dq)) continue;
-      const double d2 = dist2(p, dq);
-      if (d2 < bd || (d2 == bd && e < best)) {
-        bd = d2;
-        best = e;
-        for (int a = 0; a < 4; ++a) bdq[a] = dq[a];
+      const double *r = stage + k * RS;
+      double l[4];
+      if (map4_l(p, r, P, l)) {
+        double dq[4];
+        map4_q(r, l, dq);
+        const double d2 = dist2(p, dq);
+        if (d2 < bd || (d2 == bd && e < best)) {
+          bd = d2;
+          best = e;
+          for (int a = 0; a < 4; ++a) bdq[a] = dq[a];
+        }
       }
     }
   }
@@ -369,18 +426,13 @@ __device__ __forceinline__ int query4(const KP &p, const double *__restrict__ re
 
 // ------------------------------------------------------- interpolations
 
-template <typename FT>
-__device__ __forceinline__ FT Fat(const KP &p, const FT *__restrict__ F,
-                                  const int g[4]) {
-  const int i = ((g[0] % p.ns) + p.ns) % p.ns, j = ((g[1] % p.ns) + p.ns) % p.ns;
-  if (g[2] < 0 || g[2] >= p.nv || g[3] < 0 || g[3] >= p.nv) return (FT)0;
-  return F[(((size_t)g[3] * p.nv + g[2]) * p.ns + j) * p.ns + i];
-}
-
 // 15-point second-order interpolation (section 2.2.1 in four dimensions):
 // nearest node, its 8 axis neighbours (Lagrange signs), and one cross term
 // per axis pair at the floor corner of that plane.  x, y positions clamped
-// to [-12, ns + 11]; zero outside the u, w grid.
+// to [-12, ns + 11] and wrapped; zero outside the u, w grid.  Every stencil
+// index along an axis is the nearest node's -1, 0 or +1 (the floor corner
+// is the nearest node or the one below), so the wrapped offsets of the
+// three are formed once per axis.
 template <typename FT>
 __device__ __forceinline__ FT int15(const KP &p, const FT *__restrict__ F,
                                     const double sin_[4]) {
@@ -397,35 +449,54 @@ __device__ __forceinline__ FT int15(const KP &p, const FT *__restrict__ F,
   for (int a = 0; a < 4; ++a) {
     const double fn = floor(s[a] + 0.5);
     n[a] = (int)fn;
-    cf[a] = (int)floor(s[a]);
+    cf[a] = (int)floor(s[a]) - n[a] + 1;  // 0 or 1: index of the floor node
     dq[a] = (FT)(s[a] - fn);
   }
+  // element offsets of nodes n-1, n, n+1 per axis (-1: off the u, w grid)
+  const long long str[4] = {1, p.ns, (long long)p.ns * p.ns,
+                            (long long)p.ns * p.ns * p.nv};
+  long long off[4][3];
+  for (int a = 0; a < 4; ++a) {
+    for (int q = 0; q < 3; ++q) {
+      int i = n[a] - 1 + q;
+      if (a < 2) {
+        i = ((i % p.ns) + p.ns) % p.ns;
+        off[a][q] = (long long)i * str[a];
+      } else {
+        off[a][q] = (i >= 0 && i < p.nv) ? (long long)i * str[a] : -1;
+      }
+    }
+  }
+  auto at = [&](int q0, int q1, int q2, int q3) -> FT {
+    if (off[2][q2] < 0 || off[3][q3] < 0) return (FT)0;
+    return F[off[0][q0] + off[1][q1] + off[2][q2] + off[3][q3]];
+  };
   FT w0 = (FT)1 - dq[0] * dq[0];
   for (int a = 1; a < 4; ++a) w0 = w0 - dq[a] * dq[a];
-  FT f = Fat<FT>(p, F, n) * w0;
+  FT f = at(1, 1, 1, 1) * w0;
   for (int a = 0; a < 4; ++a) {
     const FT h = (FT)0.5 * dq[a];
     const FT wp = h * ((FT)1 + dq[a]), wm = h * ((FT)1 - dq[a]);
-    int g[4] = {n[0], n[1], n[2], n[3]};
-    g[a] = n[a] + 1;
-    f = fma(Fat<FT>(p, F, g), wp, f);
-    g[a] = n[a] - 1;
-    f = fma(-Fat<FT>(p, F, g), wm, f);
+    int qp[4] = {1, 1, 1, 1}, qm[4] = {1, 1, 1, 1};
+    qp[a] = 2;
+    qm[a] = 0;
+    f = fma(at(qp[0], qp[1], qp[2], qp[3]), wp, f);
+    f = fma(-at(qm[0], qm[1], qm[2], qm[3]), wm, f);
   }
   for (int a = 0; a < 4; ++a)
     for (int b = a + 1; b < 4; ++b) {
-      int g[4] = {n[0], n[1], n[2], n[3]};
-      g[a] = cf[a] + 1;
-      g[b] = cf[b] + 1;
-      const FT f11 = Fat<FT>(p, F, g);
-      g[a] = cf[a];
-      g[b] = cf[b];
-      const FT f00 = Fat<FT>(p, F, g);
-      g[a] = cf[a] + 1;
-      const FT f10 = Fat<FT>(p, F, g);
-      g[a] = cf[a];
-      g[b] = cf[b] + 1;
-      const FT f01 = Fat<FT>(p, F, g);
+      int q[4] = {1, 1, 1, 1};
+      q[a] = cf[a] + 1;
+      q[b] = cf[b] + 1;
+      const FT f11 = at(q[0], q[1], q[2], q[3]);
+      q[a] = cf[a];
+      q[b] = cf[b];
+      const FT f00 = at(q[0], q[1], q[2], q[3]);
+      q[a] = cf[a] + 1;
+      const FT f10 = at(q[0], q[1], q[2], q[3]);
+      q[a] = cf[a];
+      q[b] = cf[b] + 1;
+      const FT f01 = at(q[0], q[1], q[2], q[3]);
       const FT cross = ((f11 + f00) - f10) - f01;
       f = fma(cross, dq[a] * dq[b], f);
     }
@@ -533,17 +604,18 @@ __global__ __launch_bounds__(256) void k4_recon(
   __shared__ double sf[256];
   const long long blk = blockIdx.x;
   const int t = threadIdx.x;
-  int g[4];
+  int g[4], bb[4];
   double P[4];
-  block_site(p, blk, t, g, P);
-  const int n = cnt[blk];
+  long long list;
+  const bool live = block_site(p, blk, t, g, P, bb, list);
+  const int n = cnt[list];
   const bool scan_all = (n > p.cap) || (flags[0] & FL_WIDE);
   double dq[4];
-  const int best = query4(p, rec, lst + blk * p.cap, n, scan_all, P, dq, stage);
+  const int best = query4(p, rec, lst + list * p.cap, n, scan_all, P, dq, stage);
   const size_t site =
       (((size_t)g[3] * p.nv + g[2]) * p.ns + g[1]) * p.ns + g[0];
   FT fv = (FT)0;
-  if (MODE != M_ASSIGN && best >= 0) {
+  if (MODE != M_ASSIGN && live && best >= 0) {
     int k[4];
     lat_index(p, best, k);
     double Q[4], s[4];
@@ -551,21 +623,18 @@ __global__ __launch_bounds__(256) void k4_recon(
     index_pos(p, Q, s);
     fv = int15<FT>(p, F, s);
   }
-  if (MODE == M_F) fout[site] = fv;
-  if (MODE == M_ASSIGN) aout[site] = best;
+  if (MODE == M_F && live) fout[site] = fv;
+  if (MODE == M_ASSIGN && live) aout[site] = best;
   if (MODE == M_DENSITY) {
-    sf[t] = (double)fv;
+    sf[t] = (double)fv;  // 0 off the grid
     __syncthreads();
-    if (t < 16) {
+    const int i = blk_first(p, 0, bb[0]) + (t & 3);
+    const int j = blk_first(p, 1, bb[1]) + ((t >> 2) & 3);
+    if (t < 16 && i >= 0 && i < p.ns && j >= 0 && j < p.ns) {
       double s = 0.0;
       for (int l = 0; l < 4; ++l)
         for (int k = 0; k < 4; ++k) s += sf[l * 64 + k * 16 + t];
-      long long b = blk;
-      const int bx = (int)(b % p.nbs);
-      b /= p.nbs;
-      const int by = (int)(b % p.nbs);
-      const long long vb = b / p.nbs;  // bu + nbv bw
-      const int i = BLK * bx + (t & 3), j = BLK * by + (t >> 2);
+      const long long vb = (long long)bb[3] * p.nb[2] + bb[2];
       part[(size_t)vb * p.ns * p.ns + (size_t)j * p.ns + i] = s;
     }
   }
@@ -584,13 +653,15 @@ __global__ __launch_bounds__(256) void k4_remap(
   __shared__ double stage[STAGE * RS];
   const long long blk = blockIdx.x;
   const int t = threadIdx.x;
-  int g[4];
+  int g[4], bb[4];
   double P[4];
-  block_site(p, blk, t, g, P);
-  const int n = cnt[blk];
+  long long list;
+  const bool live = block_site(p, blk, t, g, P, bb, list);
+  const int n = cnt[list];
   const bool scan_all = (n > p.cap) || (flags[0] & FL_WIDE);
   double dq[4];
-  const int best = query4(p, rec, lst + blk * p.cap, n, scan_all, P, dq, stage);
+  const int best = query4(p, rec, lst + list * p.cap, n, scan_all, P, dq, stage);
+  if (!live) return;
   const size_t site =
       (((size_t)g[3] * p.nv + g[2]) * p.ns + g[1]) * p.ns + g[0];
   const bool edge = g[2] == 0 || g[2] == p.nv - 1 || g[3] == 0 || g[3] == p.nv - 1;
@@ -657,7 +728,7 @@ __global__ __launch_bounds__(256) void k4_rho(KP p, const double *__restrict__ p
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int n2 = p.ns * p.ns;
   if (q >= n2) return;
-  const int nvb = p.nbv * p.nbv;
+  const int nvb = p.nb[2] * p.nb[3];
   double s = 0.0;
   for (int v = 0; v < nvb; ++v) s += part[(size_t)v * n2 + q];
   rho[q] = (p.du * p.du) * s;
@@ -840,19 +911,22 @@ __global__ __launch_bounds__(256) void k4_kick(KP p, double *__restrict__ st,
   if (e >= p.E) return;
   const size_t E = (size_t)p.E;
   double s[NST];
-#pragma unroll 4
+#pragma unroll
   for (int q = 0; q < NST; ++q) s[q] = st[q * E + e];
   double fv[12];
   tsc12(p, fld, s[S_P], s[S_P + 1], fv);
   const double dt = p.dt;
+#pragma unroll
   for (int i = 0; i < 2; ++i) {
     const double a = fv[i], g0 = fv[2 + 2 * i], g1 = fv[3 + 2 * i];
     const double h00 = fv[6 + 3 * i], h01 = fv[7 + 3 * i], h11 = fv[8 + 3 * i];
     s[S_P + 2 + i] = fma(dt, a, s[S_P + 2 + i]);
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
       const double v = fma(g1, s[S_T + 4 + j], g0 * s[S_T + j]);
       s[S_T + 4 * (2 + i) + j] = fma(dt, v, s[S_T + 4 * (2 + i) + j]);
     }
+#pragma unroll
     for (int q = 0; q < 10; ++q) {
       const int jb = PB[q], kc = PC[q];
       const double t0j = s[S_T + jb], t1j = s[S_T + 4 + jb];
@@ -866,7 +940,7 @@ __global__ __launch_bounds__(256) void k4_kick(KP p, double *__restrict__ st,
     }
   }
   drift4(p, s, p.h);
-#pragma unroll 4
+#pragma unroll
   for (int q = 0; q < NST; ++q) st[q * E + e] = s[q];
 }
 

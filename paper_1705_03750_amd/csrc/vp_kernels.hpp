@@ -649,12 +649,12 @@ __device__ __forceinline__ double clamp_periodic(const KP &p, double sx) {
 // Six-point second-order interpolation (section 2.2.1, eq. int1 with the
 // Lagrange signs) of F at index-space position (sx, sv).  F points at the
 // grid origin of a zero-padded array.
-template <typename FT>
+template <typename FT, int PER>
 __device__ __forceinline__ FT int1(const KP &p, const FT *__restrict__ F,
                                    double sx, double sv) {
-  if (p.per) sx = clamp_periodic(p, sx);
+  if (PER) sx = clamp_periodic(p, sx);
   const double fin = floor(sx + 0.5), fjn = floor(sv + 0.5);
-  if (!((p.per || (fin >= -1.0 && fin <= (double)p.nx)) && fjn >= -1.0 &&
+  if (!((PER || (fin >= -1.0 && fin <= (double)p.nx)) && fjn >= -1.0 &&
         fjn <= (double)p.nv))
     return (FT)0;
   const double fic = floor(sx), fjc = floor(sv);
@@ -693,15 +693,15 @@ __device__ __forceinline__ void bspline_w(double ud, FT b[4]) {
 
 // Cubic B-spline value (section 2.2.2) from coefficients C (padded, with
 // mirror ghosts one site deep) at index-space position (sx, sv).
-template <typename FT>
+template <typename FT, int PER>
 __device__ __forceinline__ FT spline_eval(const KP &p, const FT *__restrict__ C,
                                           double sx, double sv) {
-  if (p.per) sx = clamp_periodic(p, sx);
-  if (!((p.per || (sx >= 0.0 && sx <= (double)(p.nx - 1))) && sv >= 0.0 &&
+  if (PER) sx = clamp_periodic(p, sx);
+  if (!((PER || (sx >= 0.0 && sx <= (double)(p.nx - 1))) && sv >= 0.0 &&
         sv <= (double)(p.nv - 1)))
     return (FT)0;
   int i = (int)floor(sx), j = (int)floor(sv);
-  if (!p.per && i > p.nx - 2) i = p.nx - 2;
+  if (!PER && i > p.nx - 2) i = p.nx - 2;
   if (j > p.nv - 2) j = p.nv - 2;
   FT bx[4], bv[4];
   bspline_w<FT>(sx - (double)i, bx);
@@ -1343,7 +1343,7 @@ __device__ __forceinline__ void recon_tile(
   double f = 0.0, em = 0.0;
   int best = -1;
   if (blk_ok) {
-    const int b = bv * p.nbx + list_bx(p, bx);
+    const int b = bv * p.nbx + (PER ? list_bx(p, bx) : bx);
     const int *L = lst + (size_t)b * p.cap;
     const int id0 = list_head(p, L);
     const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
@@ -1359,7 +1359,7 @@ __device__ __forceinline__ void recon_tile(
       const double sx = (Qx - p.x_min) * p.inv_dx - 0.5;
       const double sv = (Qv - p.v_min) * p.inv_dv - 0.5;
       const FT *F0 = F + (long)PV * p.pitch + PX;
-      const FT fv = int1<FT>(p, F0, sx, sv);
+      const FT fv = int1<FT, PER>(p, F0, sx, sv);
       f = (double)fv;
       if (MODE == MODE_F) fout[(size_t)j * p.nx + i] = fv;
     } else if (MODE == MODE_F && live) {
@@ -1474,7 +1474,7 @@ __device__ __forceinline__ void remap_tile(
   const int i = group_ox(p, gy) + 8 * (bx - 1) + (lane & 7);
   const int j = p.ov + 8 * (bv - p.obv) + (lane >> 3);
   const bool live = i >= 0 && i < p.nx && j >= 0 && j < p.nv;
-  const int b = bv * p.nbx + list_bx(p, bx);
+  const int b = bv * p.nbx + (PER ? list_bx(p, bx) : bx);
   const int *L = lst + (size_t)b * p.cap;
   const int id0 = list_head(p, L);
   const int n = __builtin_amdgcn_readfirstlane(cnt[b]);
@@ -1525,7 +1525,7 @@ __device__ __forceinline__ void remap_tile(
     const double sx = (Qx - p.x_min) * p.inv_dx - 0.5;
     const double sv = (Qv - p.v_min) * p.inv_dv - 0.5;
     const FT *C0 = C + (long)PV * p.pitch + PX;
-    val = spline_eval<FT>(p, C0, sx, sv);
+    val = spline_eval<FT, PER>(p, C0, sx, sv);
   }
   if (TO_F == 0)
     Fout[(long)(j + PV) * p.pitch + (i + PX)] = val;
