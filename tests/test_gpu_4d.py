@@ -142,3 +142,45 @@ def test_validation(v4):
                 dict(ns=16, nv=8, L=1.0, vmax=1.0, ss=4, sv=4, dt=0.0)):
         with pytest.raises(v4.VP4Error):
             v4.VlasovRun4(device="cuda:0", **bad)
+
+
+@pytest.mark.timeout(600)
+def test_q4_bench_size(v4, o4):
+    """The 4D benchmark workload at its size (64^4 sites, elements every 4th
+    site, the launch shapes the benchmark times): one step in FP64, then
+    every element and every site against the oracle, bit for bit; the mixed
+    engine within rel L2 1e-5 of the oracle's f.  The oracle takes about
+    1.5 minutes here."""
+    import time
+    import torch
+    import workloads as W
+    t0 = time.time()
+    ns = nv = 64
+    L, vmax = 4.0 * math.pi, 6.0
+    f0 = W.landau4(ns, nv, L, vmax, 0.05, seed=1)
+    p = dict(ns=ns, nv=nv, L=L, vmax=vmax, ss=4, sv=4, G=-0.5, dt=0.1,
+             n_s=10)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        print(f"[q4 64^4] engine {prec} at {time.time() - t0:.1f} s",
+              flush=True)
+        g = v4.VlasovRun4(device="cuda:0", precision=prec, **p)
+        g.init_conditions(torch.as_tensor(f0, device="cuda:0"))
+        g.step(1)
+        out[prec] = (g.get_elements().cpu().numpy(),
+                     g.reconstruct_f().cpu().numpy())
+        g.sync()
+        g.close()
+        del g
+    torch.cuda.empty_cache()
+    print(f"[q4 64^4] oracle at {time.time() - t0:.1f} s", flush=True)
+    o = o4.Oracle4(**p)
+    o.init_conditions(f0)
+    o.step(1)
+    print(f"[q4 64^4] oracle stepped at {time.time() - t0:.1f} s", flush=True)
+    assert np.array_equal(out["fp64"][0], o.get_elements())
+    f_ref = o.reconstruct_f()
+    print(f"[q4 64^4] oracle f at {time.time() - t0:.1f} s", flush=True)
+    assert np.array_equal(out["fp64"][1], f_ref)
+    fm = out["mixed"][1].astype(np.float64)
+    assert np.linalg.norm(fm - f_ref) / np.linalg.norm(f_ref) <= 1e-5
