@@ -216,21 +216,46 @@ def four_d_leg(steps: int = 20):
             "mass": d["mass"], "energy": d["energy"]}
 
 
-def cpu_baseline(cfg, f0, steps: int, threads: int):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, f0, steps: int, threads: int, single_steps: int):
+    """The oracle on the host: `steps` steps with `threads` OpenMP threads
+    (the reported value), then `single_steps` steps on one thread."""
     import oracle
-    used = oracle.set_threads(threads)
     p = cfg.params()
     p.pop("precision")
-    o = oracle.Oracle(**p)
-    o.init_conditions(f0)
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    return {"value": cfg.n * cfg.n * steps / dt, "unit": "site updates/s",
-            "cores": used, "kind": "oracle",
-            "sample": f"{steps} steps of the same 2048^2 run from t = 0 "
-                      f"(remap at step {cfg.n_s} included when reached), "
-                      f"{dt:.2f} s wall"}
+    rates = {}
+    for nthr, nst in ((threads, steps), (1, single_steps)):
+        if nst <= 0:
+            continue
+        used = oracle.set_threads(nthr)
+        o = oracle.Oracle(**p)
+        o.init_conditions(f0)
+        t0 = time.perf_counter()
+        o.step(nst)
+        rates[nthr] = (used, nst, time.perf_counter() - t0)
+    used, nst, dt = rates[threads]
+    out = {"value": cfg.n * cfg.n * nst / dt, "unit": "site updates/s",
+           "cores": used, "kind": "oracle",
+           "sample": f"{nst} steps of the same 2048^2 run from t = 0 "
+                     f"(remap at step {cfg.n_s} included when reached), "
+                     f"{dt:.2f} s wall",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if 1 in rates and threads != 1:
+        _, n1, dt1 = rates[1]
+        out["single_thread"] = {"value": cfg.n * cfg.n * n1 / dt1,
+                                "steps": n1, "seconds": dt1}
+    oracle.set_threads(threads)
+    return out
 
 
 def serve_leg(count: int, step_scale: float, seed: int, occupancy: float,
@@ -317,6 +342,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-single-steps", type=int, default=8)
     ap.add_argument("--cpu-threads", type=int,
                     default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
@@ -443,7 +469,8 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, f0, args.cpu_steps,
-                                           args.cpu_threads)
+                                           args.cpu_threads,
+                                           args.cpu_single_steps)
     print(json.dumps(out))
 
 

@@ -678,41 +678,58 @@ __global__ __launch_bounds__(256) void k4_remap(
     hi[a] = (z < -p.beta) ? 0 : 1;
     three = three || (hi[a] - lo[a] == 2);
   }
+  // The beta-set in the order of the nested loops over the offsets (axis 3
+  // slowest, axis 0 fastest), one slot per trip so that a wavefront runs at
+  // most 16 neighbour maps whatever its lanes' sets: without a three-valued
+  // axis the 16 corners d_a = lo_a + bit a of q; with one, the 9 slots
+  // -1 on axes 3, 2, 1, 0, the centre, +1 on axes 0, 1, 2, 3, those outside
+  // [lo, hi] skipped.
   double sw = 0.0, sq[4] = {0.0, 0.0, 0.0, 0.0};
-  int d[4];
-  for (d[3] = lo[3]; d[3] <= hi[3]; ++d[3])
-    for (d[2] = lo[2]; d[2] <= hi[2]; ++d[2])
-      for (d[1] = lo[1]; d[1] <= hi[1]; ++d[1])
-        for (d[0] = lo[0]; d[0] <= hi[0]; ++d[0]) {
-          const int nz = (d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0);
-          if (three && nz > 1) continue;
-          int kk[4];
-          double shift[4] = {0.0, 0.0, 0.0, 0.0};
-          bool ok = true;
-          for (int a = 0; a < 4; ++a) {
-            int k = k0[a] + d[a];
-            const int nl = a < 2 ? p.ms : p.mv;
-            if (k < 0 || k >= nl) {
-              if (a >= 2) {
-                ok = false;
-                break;
-              }
-              shift[a] = (k < 0) ? -p.L : p.L;
-              k = (k < 0) ? k + nl : k - nl;
-            }
-            kk[a] = k;
-          }
-          if (!ok) continue;
-          const int m = ((kk[3] * p.mv + kk[2]) * p.ms + kk[1]) * p.ms + kk[0];
-          double ex[4];
-          map4(p, rec + (size_t)m * RS, P, ex);
-          const double wgt = Wk(2.0 * sqrt(dist2(p, ex)));
-          sw += wgt;
-          for (int a = 0; a < 4; ++a) {
-            const double Qa = (lat_q(p, a, kk[a]) + shift[a]) + ex[a];
-            sq[a] = fma(wgt, Qa, sq[a]);
-          }
+  for (int q = 0; q < 16; ++q) {
+    int d[4];
+    bool use = !three || q == 4;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (!three) {
+        d[a] = lo[a] + ((q >> a) & 1);
+      } else if (q == 3 - a) {
+        d[a] = -1;
+        use = lo[a] == -1;
+      } else if (q == 5 + a) {
+        d[a] = 1;
+        use = hi[a] == 1;
+      } else {
+        d[a] = 0;
+      }
+    }
+    if (!use) continue;
+    int kk[4];
+    double shift[4] = {0.0, 0.0, 0.0, 0.0};
+    bool ok = true;
+    for (int a = 0; a < 4; ++a) {
+      int k = k0[a] + d[a];
+      const int nl = a < 2 ? p.ms : p.mv;
+      if (k < 0 || k >= nl) {
+        if (a >= 2) {
+          ok = false;
+          break;
         }
+        shift[a] = (k < 0) ? -p.L : p.L;
+        k = (k < 0) ? k + nl : k - nl;
+      }
+      kk[a] = k;
+    }
+    if (!ok) continue;
+    const int m = ((kk[3] * p.mv + kk[2]) * p.ms + kk[1]) * p.ms + kk[0];
+    double ex[4];
+    map4(p, rec + (size_t)m * RS, P, ex);
+    const double wgt = Wk(2.0 * sqrt(dist2(p, ex)));
+    sw += wgt;
+    for (int a = 0; a < 4; ++a) {
+      const double Qa = (lat_q(p, a, kk[a]) + shift[a]) + ex[a];
+      sq[a] = fma(wgt, Qa, sq[a]);
+    }
+  }
   double Q[4], s[4];
   for (int a = 0; a < 4; ++a)
     Q[a] = (sw > 0.0) ? sq[a] / sw : lat_q(p, a, k0[a]) + dq[a];

@@ -1495,24 +1495,38 @@ __device__ __forceinline__ void remap_tile(
     const int xlo = (zx < beta) ? -1 : 0, xhi = (zx < -beta) ? 0 : 1;
     const int vlo = (zv < beta) ? -1 : 0, vhi = (zv < -beta) ? 0 : 1;
     const bool three = (xhi - xlo == 2) || (vhi - vlo == 2);
+    // The beta-set in the order of the nested loops (v offset slowest), one
+    // slot per trip so that a wavefront runs at most 4 or 5 neighbour maps
+    // whatever its lanes' sets: without a three-valued axis the 4 corners;
+    // with one, the 5 slots (dl, dk) = (-1, 0), (0, -1), (0, 0), (0, 1),
+    // (1, 0), those outside the axis ranges skipped.
     double sw = 0.0, sqx = 0.0, sqv = 0.0;
-    for (int dl = vlo; dl <= vhi; ++dl) {
-      for (int dk = xlo; dk <= xhi; ++dk) {
-        if (three && dk != 0 && dl != 0) continue;
-        double shift;
-        const int k = lattice_col(p, k0 + dk, shift), l = l0 + dl;
-        if (k < 0 || l < 0 || l >= p.mv) continue;
-        const size_t m = (size_t)(l * p.mx + k);
-        double ex, ev;
-        element_map<PER>(p, rec + m * RS, xP, vP, ex, ev);
-        const double qx = (qm[2 * m] + shift) + ex, qv = qm[2 * m + 1] + ev;
-        const double ax = ex * p.rx, av = ev * p.rv;
-        const double d = sqrt(fma(ax, ax, av * av));
-        const double wt = W_kernel(2.0 * d);
-        sw += wt;
-        sqx = fma(wt, qx, sqx);
-        sqv = fma(wt, qv, sqv);
+    for (int q = 0; q < 5; ++q) {
+      int dk, dl;
+      bool use;
+      if (!three) {
+        dk = xlo + (q & 1);
+        dl = vlo + (q >> 1);
+        use = q < 4;
+      } else {
+        dk = (q == 1) ? -1 : (q == 3) ? 1 : 0;
+        dl = (q == 0) ? -1 : (q == 4) ? 1 : 0;
+        use = dk >= xlo && dk <= xhi && dl >= vlo && dl <= vhi;
       }
+      if (!use) continue;
+      double shift;
+      const int k = lattice_col(p, k0 + dk, shift), l = l0 + dl;
+      if (k < 0 || l < 0 || l >= p.mv) continue;
+      const size_t m = (size_t)(l * p.mx + k);
+      double ex, ev;
+      element_map<PER>(p, rec + m * RS, xP, vP, ex, ev);
+      const double qx = (qm[2 * m] + shift) + ex, qv = qm[2 * m + 1] + ev;
+      const double ax = ex * p.rx, av = ev * p.rv;
+      const double d = sqrt(fma(ax, ax, av * av));
+      const double wt = W_kernel(2.0 * d);
+      sw += wt;
+      sqx = fma(wt, qx, sqx);
+      sqv = fma(wt, qv, sqv);
     }
     double Qx, Qv;
     if (sw > 0.0) {

@@ -83,6 +83,14 @@ def test_c2_full_size_mixed(vp, orc):
     f_gpu = g.reconstruct_f().cpu().numpy().astype(np.float64)
     l2 = np.linalg.norm(f_gpu - f_ref) / np.linalg.norm(f_ref)
     assert l2 <= 1e-5, l2
+    # Along its own trajectory the mixed run's elements differ from the
+    # oracle's at ~1e-7 relative, so only sites whose two best distances lie
+    # that close can change hands: report the fraction, bound it loosely.
+    a_ref = o.assignment(False)
+    differs = float(np.mean(g.assignment().cpu().numpy() != a_ref))
+    print(f"[c2 mixed] sites assigned differently after 30 steps: "
+          f"{differs:.2e}", flush=True)
+    assert differs <= 1e-4, differs
     g.set_elements(o.get_elements())
     assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(False))
     g.sync()
