@@ -179,6 +179,12 @@ struct vp_ctx {
   int64_t step;
   bool ready;
   int cur = 0;  // which of the two block-count buffers holds the live lists
+  // The spline fit after a resampling runs on `aux` while the following
+  // steps run on `stream` (they read F_ini, not the coefficients); it is
+  // joined (`fit_pending`) before anything reads or restages C or T.
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_eval = nullptr, ev_fit = nullptr;
+  bool fit_pending = false;
   int coop_grid = 0;     // largest co-resident grid of k_elem_field_coop
   int64_t fsync_target = 0;  // chunks published so far through L.fsync
   int64_t reset_step = 0;  // step of the elements' last reset
@@ -216,15 +222,17 @@ struct ProfScope {
   vp_ctx *c;
   int kind;
   bool on;
-  ProfScope(vp_ctx *c_, int k) : c(c_), kind(k), on(false) {
+  hipStream_t st;
+  ProfScope(vp_ctx *c_, int k, hipStream_t s = nullptr)
+      : c(c_), kind(k), on(false), st(s ? s : c_->stream) {
     if (c->prof && c->ev_used[kind] < c->prof_cap) {
       on = true;
-      (void)hipEventRecord(c->ev[kind][2 * c->ev_used[kind]], c->stream);
+      (void)hipEventRecord(c->ev[kind][2 * c->ev_used[kind]], st);
     }
   }
   ~ProfScope() {
     if (on) {
-      (void)hipEventRecord(c->ev[kind][2 * c->ev_used[kind] + 1], c->stream);
+      (void)hipEventRecord(c->ev[kind][2 * c->ev_used[kind] + 1], st);
       c->ev_used[kind] += 1;
     }
   }
@@ -404,37 +412,37 @@ int launch_reset(vp_ctx *c) {
 }
 
 template <typename FT>
-int fit_spline_t(vp_ctx *c) {
+int fit_spline_t(vp_ctx *c, hipStream_t st) {
   const KP &k = c->k;
-  ProfScope ps(c, PK_FIT);
+  ProfScope ps(c, PK_FIT, st);
   FT *tab = c->at<FT>(c->L.tab);
   FT *cpx = tab, *rix = tab + k.nx, *cpv = tab + 2 * k.nx,
      *riv = tab + 2 * k.nx + k.nv, *zx = tab + 2 * k.nx + 2 * k.nv,
      *den = tab + 3 * k.nx + 2 * k.nv;
   hipLaunchKernelGGL((k_fit_x<FT>), dim3(grid_for(k.nv, FIT_LINES)),
                      dim3(FIT_THREADS), 0,
-                     c->stream, k, c->at<FT>(c->L.F), c->at<FT>(c->L.T), cpx,
+                     st, k, c->at<FT>(c->L.F), c->at<FT>(c->L.T), cpx,
                      rix);
   VP_LAUNCH_CHECK(c, "k_fit_x");
   if (k.per) {
     hipLaunchKernelGGL((k_fit_x_cyclic<FT>), dim3(k.nv), dim3(256), 0,
-                       c->stream, k, c->at<FT>(c->L.T), zx, den);
+                       st, k, c->at<FT>(c->L.T), zx, den);
     VP_LAUNCH_CHECK(c, "k_fit_x_cyclic");
   }
   hipLaunchKernelGGL((k_fit_v<FT>), dim3(grid_for(k.nx, FIT_LINES)),
                      dim3(FIT_THREADS), 0,
-                     c->stream, k, c->at<FT>(c->L.T), c->at<FT>(c->L.C), cpv,
+                     st, k, c->at<FT>(c->L.T), c->at<FT>(c->L.C), cpv,
                      riv);
   VP_LAUNCH_CHECK(c, "k_fit_v");
   if (k.per) {
     hipLaunchKernelGGL((k_ghost_periodic<FT>), dim3(grid_for(k.nv + 2, 256)),
-                       dim3(256), 0, c->stream, k, c->at<FT>(c->L.C), -1,
+                       dim3(256), 0, st, k, c->at<FT>(c->L.C), -1,
                        k.nv);
     VP_LAUNCH_CHECK(c, "k_ghost_periodic");
     return VP_OK;
   }
   hipLaunchKernelGGL((k_ghost_x<FT>), dim3(grid_for(k.nv + 2, 256)), dim3(256),
-                     0, c->stream, k, c->at<FT>(c->L.C));
+                     0, st, k, c->at<FT>(c->L.C));
   VP_LAUNCH_CHECK(c, "k_ghost_x");
   return VP_OK;
 }
@@ -454,12 +462,51 @@ int ghost_F(vp_ctx *c) {
   return c->mixed() ? ghost_F_t<float>(c) : ghost_F_t<double>(c);
 }
 
-int fit_spline(vp_ctx *c) {
-  return c->mixed() ? fit_spline_t<float>(c) : fit_spline_t<double>(c);
+int fit_spline(vp_ctx *c, hipStream_t st = nullptr) {
+  if (!st) st = c->stream;
+  return c->mixed() ? fit_spline_t<float>(c, st) : fit_spline_t<double>(c, st);
+}
+
+// Wait (on the context's stream) for a spline fit still running on aux.
+int join_fit(vp_ctx *c) {
+  if (!c->fit_pending) return VP_OK;
+  c->fit_pending = false;
+  const hipError_t e = hipStreamWaitEvent(c->stream, c->ev_fit, 0);
+  if (e != hipSuccess) return dev_fail(c, e, "join spline fit");
+  return VP_OK;
+}
+
+// The spline fit of a resampling, overlapped with the steps that follow it
+// (they read F_ini only).  Synchronous on the context's stream while that
+// stream is being captured into a graph.
+int fit_spline_async(vp_ctx *c) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess ||
+      cs != hipStreamCaptureStatusNone)
+    return fit_spline(c);
+  hipError_t e = hipSuccess;
+  if (!c->aux) {
+    e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(&c->ev_eval, hipEventDisableTiming);
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(&c->ev_fit, hipEventDisableTiming);
+    if (e != hipSuccess) return dev_fail(c, e, "fit stream");
+  }
+  e = hipEventRecord(c->ev_eval, c->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_eval, 0);
+  if (e != hipSuccess) return dev_fail(c, e, "fit stream order");
+  const int rc = fit_spline(c, c->aux);
+  if (rc) return rc;
+  e = hipEventRecord(c->ev_fit, c->aux);
+  if (e != hipSuccess) return dev_fail(c, e, "fit stream order");
+  c->fit_pending = true;
+  return VP_OK;
 }
 
 template <typename FT, int TO_F>
 int launch_remap_t(vp_ctx *c, void *fout) {
+  if (const int rc = join_fit(c)) return rc;
   ProfScope ps(c, PK_REMAP);
   FT *out = TO_F ? reinterpret_cast<FT *>(fout) : c->at<FT>(c->L.F);
   auto kern = c->k.per ? k_remap_eval<FT, TO_F, 1> : k_remap_eval<FT, TO_F, 0>;
@@ -481,7 +528,7 @@ int do_remap(vp_ctx *c) {
                   : launch_remap_t<double, 0>(c, nullptr);
   if (rc) return rc;
   if ((rc = ghost_F(c))) return rc;
-  if ((rc = fit_spline(c))) return rc;
+  if ((rc = fit_spline_async(c))) return rc;
   c->reset_step = c->step;
   return launch_reset(c);
 }
@@ -788,15 +835,22 @@ int vp_create(const vp_params *p, void *dev_workspace, size_t bytes,
 
 int vp_destroy(vp_ctx *c) {
   if (!c) return VP_EINVAL;
+  const int rc = join_fit(c);
   const hipError_t e = hipStreamSynchronize(c->stream);
+  if (c->aux) {
+    (void)hipEventDestroy(c->ev_eval);
+    (void)hipEventDestroy(c->ev_fit);
+    (void)hipStreamDestroy(c->aux);
+  }
   delete c;
-  return e == hipSuccess ? VP_OK : VP_EDEVICE;
+  return (e == hipSuccess && !rc) ? VP_OK : VP_EDEVICE;
 }
 
 int vp_init_conditions(vp_ctx *c, const double *f0, int f0_on_device) {
   if (!c || !f0) return VP_EINVAL;
   const int nx = c->k.nx, nv = c->k.nv;
   int rc;
+  if ((rc = join_fit(c))) return rc;
   if (f0_on_device) {
     if ((rc = load_rows(c, f0, 0, nv))) return rc;
   } else {
@@ -949,6 +1003,7 @@ int vp_prof_begin(vp_ctx *c, int max_launches) {
 
 int vp_prof_end(vp_ctx *c, double *ms, int64_t *n) {
   if (!c || !c->prof) return VP_EINVAL;
+  if (const int rc = join_fit(c)) return rc;
   hipError_t r = hipStreamSynchronize(c->stream);
   int rc = VP_OK;
   if (r != hipSuccess) rc = dev_fail(c, r, "prof sync");
@@ -973,6 +1028,7 @@ int vp_prof_end(vp_ctx *c, double *ms, int64_t *n) {
 
 int vp_sync(vp_ctx *c) {
   if (!c) return VP_EINVAL;
+  if (const int rc = join_fit(c)) return rc;
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return dev_fail(c, e, "sync");
   return check_flags(c);
