@@ -33,8 +33,15 @@
  * Memory and streams: the library allocates no device memory.  The caller
  * passes one device workspace of vp_footprint() bytes (any allocator, e.g. a
  * torch uint8 tensor) and a HIP stream; every call enqueues its work on that
- * stream and returns without waiting unless stated.  Pointers named "dev"
- * are device pointers; "host" ones are host pointers.  The caller keeps the
+ * stream and returns without waiting unless stated.  One exception: the
+ * spline fit that follows a resampling inside vp_step runs on a stream the
+ * context creates (default priority), overlapped with the following steps,
+ * which read F_ini but not the coefficients; the context's stream waits for
+ * it before the coefficients are next read or restaged (the next
+ * resampling, vp_reconstruct_f scheme 1, vp_init_conditions) and in
+ * vp_sync, vp_prof_end and vp_destroy.  While the context's stream is being
+ * captured into a graph the fit stays on it.  Pointers named "dev" are
+ * device pointers; "host" ones are host pointers.  The caller keeps the
  * workspace alive until vp_destroy.  One host thread per context at a time.
  *
  * Errors: every call returns a status.  No exception crosses the ABI.
