@@ -240,3 +240,33 @@ def test_mixed_precision_against_fp64_oracle(vp, orc):
     drift_ref = (d_ref - e0_ref) / abs(e0_ref)
     drift_gpu = (d_gpu - e0_gpu) / abs(e0_gpu)
     assert abs(drift_gpu - drift_ref) <= 1e-6, (drift_gpu, drift_ref)
+
+
+def test_reads_right_after_a_resampling(vp, orc):
+    """The spline fit that follows a resampling inside a step overlaps the
+    next steps; every reader of the new coefficients waits for it: the remap
+    reconstruction called at once, the next resampling a few steps later, a
+    new initial condition given right after one (its host upload is staged
+    through the coefficient buffer)."""
+    f0 = halos(256, seed=11)
+    p = params(256, 4, dt=1e-3, n_s=4)
+    o, g = pair(vp, orc, p, f0)
+    o.step(4)
+    g.step(4)
+    assert rel_linf(g.reconstruct_f(1).cpu().numpy(), o.reconstruct_f(1)) <= RTOL
+    o.step(4)
+    g.step(4)
+    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    import ctypes as C
+    f1 = np.ascontiguousarray(halos(256, seed=12))
+    o.step(4)
+    g.step(4)
+    o.init_conditions(f1)
+    assert vp.lib().vp_init_conditions(
+        g.h, f1.ctypes.data_as(C.c_void_p), 0) == 0
+    o.step(5)
+    g.step(5)
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    assert rel_linf(g.reconstruct_f(1).cpu().numpy(), o.reconstruct_f(1)) <= RTOL
+    g.sync()
