@@ -486,12 +486,22 @@ int fit_spline_async(vp_ctx *c) {
     return fit_spline(c);
   hipError_t e = hipSuccess;
   if (!c->aux) {
-    e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    hipStream_t st = nullptr;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess)
-      e = hipEventCreateWithFlags(&c->ev_eval, hipEventDisableTiming);
+      e = hipEventCreateWithFlags(&ea, hipEventDisableTiming);
     if (e == hipSuccess)
-      e = hipEventCreateWithFlags(&c->ev_fit, hipEventDisableTiming);
-    if (e != hipSuccess) return dev_fail(c, e, "fit stream");
+      e = hipEventCreateWithFlags(&eb, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (eb) (void)hipEventDestroy(eb);
+      if (ea) (void)hipEventDestroy(ea);
+      if (st) (void)hipStreamDestroy(st);
+      return dev_fail(c, e, "fit stream");
+    }
+    c->aux = st;
+    c->ev_eval = ea;
+    c->ev_fit = eb;
   }
   e = hipEventRecord(c->ev_eval, c->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_eval, 0);
