@@ -270,3 +270,39 @@ def test_reads_right_after_a_resampling(vp, orc):
     assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
     assert rel_linf(g.reconstruct_f(1).cpu().numpy(), o.reconstruct_f(1)) <= RTOL
     g.sync()
+
+
+def test_contexts_are_independent(vp, orc):
+    """Two runs on two streams, their steps interleaved (and one of them
+    resampling while the other steps), give bit for bit what each gives
+    alone: a context keeps all its state in its own workspace."""
+    import torch
+    fa, fb = halos(128, seed=21), halos(96, nv=64, seed=22)
+    pa = params(128, 4, dt=1e-3, n_s=6)
+    pb = params(96, 8, nv=64, sv=4, dt=2e-3, n_s=5)
+
+    def alone(p, f):
+        g = vp.VlasovRun(device="cuda:0", **p)
+        g.init_conditions(f)
+        g.step(13)
+        out = (g.get_elements().cpu().numpy(), g.reconstruct_f().cpu().numpy())
+        g.sync()
+        return out
+
+    ref_a, ref_b = alone(pa, fa), alone(pb, fb)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ga = vp.VlasovRun(device="cuda:0", stream=sa, **pa)
+    gb = vp.VlasovRun(device="cuda:0", stream=sb, **pb)
+    ga.init_conditions(fa)
+    gb.init_conditions(fb)
+    for k in range(13):
+        ga.step(1)
+        gb.step(1)
+    ea, fa_ = ga.get_elements(), ga.reconstruct_f()
+    eb, fb_ = gb.get_elements(), gb.reconstruct_f()
+    ga.sync()
+    gb.sync()
+    assert np.array_equal(ea.cpu().numpy(), ref_a[0])
+    assert np.array_equal(fa_.cpu().numpy(), ref_a[1])
+    assert np.array_equal(eb.cpu().numpy(), ref_b[0])
+    assert np.array_equal(fb_.cpu().numpy(), ref_b[1])
