@@ -644,11 +644,9 @@ __global__ __launch_bounds__(256) void k4_recon(
 // element, beta-restricted lattice neighbours (no offsets in more than one
 // axis when an axis needs three; x, y wrap with a one-period shift), W(2d)
 // blend of their Q, tensor spline of F_ini at Q_r; u, w edge rows zero.
-// Writes into out (F_ini when resampling).  Four wavefronts per SIMD (at
-// most 128 VGPRs, no spills): the per-lane gathers of the neighbours'
-// records need the latency hiding.
+// Writes into out (F_ini when resampling).
 template <typename FT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k4_remap(
+__global__ __launch_bounds__(256) void k4_remap(
     KP p, const double *__restrict__ rec, const int *__restrict__ cnt,
     const int *__restrict__ lst, const int *__restrict__ flags,
     const FT *__restrict__ C, FT *__restrict__ out) {

@@ -120,8 +120,10 @@ __global__ __launch_bounds__(256) void kb_elem(
 
 // Reconstruction tiles (8 columns x 64 rows per item); arg = live count
 // buffer.  MODE_DENSITY also computes the force; MODE_F writes R.fout.
+// Eight wavefronts per SIMD, as the single-run kernel (the run lookup
+// would otherwise push it over 64 VGPRs).
 template <typename FT, int MODE>
-__global__ __launch_bounds__(512) void kb_recon(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void kb_recon(
     const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
   const int total = tab->total;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
