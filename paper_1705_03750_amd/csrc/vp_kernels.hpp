@@ -267,33 +267,6 @@ __device__ __forceinline__ void elem_kick(const KP &p, const Acc &acc,
   elem_drift(p, s);
 }
 
-// Can the validity window |A (P - P_m)| < (dx_m, dv_m) of an element hold a
-// site of the query block whose first site is (i0, j0)?  l = A (P - P_m) is
-// linear in P, so over the rectangle spanned by the block's sites it ranges
-// over centre +- the sum of |coefficient| x half-width in each component;
-// the block is skipped only when one component stays outside the window by
-// more than a margin that covers the rounding of l at the sites (relative
-// to the magnitudes of the products A_ij dP_j, which may cancel).
-__device__ __forceinline__ bool block_meets_window(
-    const KP &p, double X, double V, double axx, double axv, double avx,
-    double avv, int i0, int j0) {
-  // periodic x: i0 is an unwrapped column near the element, all 8 live
-  const int ia = p.per ? i0 : max(0, i0), ib = p.per ? i0 + 7 : min(p.nx - 1, i0 + 7);
-  const int ja = max(0, j0), jb = min(p.nv - 1, j0 + 7);
-  const double xa = site_x(p, ia), xb = site_x(p, ib);
-  const double va = site_v(p, ja), vb = site_v(p, jb);
-  const double cx = 0.5 * (xa + xb) - X, cv = 0.5 * (va + vb) - V;
-  const double hx = 0.5 * (xb - xa), hv = 0.5 * (vb - va);
-  const double mx = fabs(cx) + hx, mv = fabs(cv) + hv;
-  const double lxc = axx * cx + axv * cv;
-  const double rx = fabs(axx) * hx + fabs(axv) * hv;
-  const double lvc = avx * cx + avv * cv;
-  const double rv = fabs(avx) * hx + fabs(avv) * hv;
-  const double tx = 0x1p-36 * (fabs(axx) * (mx + 1.0) + fabs(axv) * (mv + 1.0) + p.dxm);
-  const double tv = 0x1p-36 * (fabs(avx) * (mx + 1.0) + fabs(avv) * (mv + 1.0) + p.dvm);
-  return fabs(lxc) - rx < p.dxm + tx && fabs(lvc) - rv < p.dvm + tv;
-}
-
 // Query record and block registration of one element.  A non-finite
 // element or det T <= 0 raises FLAG_NUMERIC and is not registered.
 __device__ __forceinline__ void elem_record(
@@ -371,29 +344,55 @@ __device__ __forceinline__ void elem_record(
   }
   // slot claims are independent: issue them sixteen at a time and only
   // then write the ids (one atomic round trip per sixteen blocks).
-  // A block of the box is listed only if the window can hold one of its
-  // sites (block_meets_window), so sheared windows do not fill the lists
-  // of the blocks their bounding box merely touches.
+  // A block of the box is listed only if the validity window |l| < (dx_m,
+  // dv_m), l = A (P - P_m), can hold one of its sites, so sheared windows
+  // do not fill the lists of the blocks their bounding box merely touches.
+  // l is linear in P: over the block's 8x8 rectangle of sites (a superset
+  // of its live sites at the grid edges) it ranges over l(centre) +- the
+  // sum of |A_ij| x half-width.  A block is skipped only when a component
+  // stays outside the window by more than a margin covering the rounding of
+  // l at the sites, relative to the magnitudes of the products A_ij dP_j
+  // (which may cancel), taken at the largest distance of a block site from
+  // the element, so that per block only l(centre) remains to compute.
+  const double hx = 3.5 * p.dx, hv = 3.5 * p.dv;
+  const double mxm = (rxs + 8.0) * p.dx, mvm = (rvs + 8.0) * p.dv;
+  const double limx =
+      p.dxm + 0x1p-36 * (fabs(axx) * (mxm + 1.0) + fabs(axv) * (mvm + 1.0) +
+                         p.dxm) + (fabs(axx) * hx + fabs(axv) * hv);
+  const double limv =
+      p.dvm + 0x1p-36 * (fabs(avx) * (mxm + 1.0) + fabs(avv) * (mvm + 1.0) +
+                         p.dvm) + (fabs(avx) * hx + fabs(avv) * hv);
+  const int ga = group_of_brow(p, b0v);
+  const int oa = group_ox(p, ga), ob = group_ox(p, ga + 1);
   constexpr int RB = 16;
   const int nblk = wxm * wv;
+  int qr = 0, qc = 0;  // block row and column of q = q0 + k in the box
   for (int q0 = 0; q0 < nblk; q0 += RB) {
     int bb[RB], slot[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-      const int q = q0 + k;
       bb[k] = -1;
-      if (q < nblk) {
-        const int bvq = b0v + q / wxm;
-        const int o = group_ox(p, group_of_brow(p, bvq));
-        const int bxq = blk(ilo, o, 1) + q % wxm;
+      if (q0 + k < nblk) {
+        const int bvq = b0v + qr;
+        const int gy = group_of_brow(p, bvq);
+        const int o = gy == ga ? oa : (gy == ga + 1 ? ob : group_ox(p, gy));
+        const int bxq = blk(ilo, o, 1) + qc;
         const int i0 = o + 8 * (bxq - 1), j0 = p.ov + 8 * (bvq - p.obv);
-        if (bxq <= blk(ihi, o, 1) &&
-            block_meets_window(p, s.x, s.v, axx, axv, avx, avv, i0, j0))
+        const double cx = (p.x_min + (double)(i0 + 4) * p.dx) - s.x;
+        const double cv = (p.v_min + (double)(j0 + 4) * p.dv) - s.v;
+        const double lxc = axx * cx + axv * cv, lvc = avx * cx + avv * cv;
+        if (bxq <= blk(ihi, o, 1) && fabs(lxc) < limx && fabs(lvc) < limv)
           bb[k] = bvq * p.nbx +
                   (p.per ? ((bxq % p.nbl) + p.nbl) % p.nbl : bxq);
+        if (++qc == wxm) {
+          qc = 0;
+          ++qr;
+        }
       }
-      slot[k] = (bb[k] >= 0) ? atomicAdd(&cnt[bb[k]], 1) : p.cap;
     }
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      slot[k] = (bb[k] >= 0) ? atomicAdd(&cnt[bb[k]], 1) : p.cap;
 #pragma unroll
     for (int k = 0; k < RB; ++k)
       if (slot[k] < p.cap) lst[(size_t)bb[k] * p.cap + slot[k]] = e;
