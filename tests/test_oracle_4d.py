@@ -9,7 +9,10 @@ mathematics and physics that do not come from it:
   (mirror axes) solves, interpolating the nodes;
 * field of a cosine density equal to the spectral solution along x, along
   y and obliquely; no force for a uniform density;
-* free streaming wraps the elements exactly; bucketed query = brute force;
+* free streaming wraps the elements exactly and drifts injected T and H by
+  t times their velocity rows; bucketed query = brute force; the validity
+  window strict per axis, and the assignment of displaced undeformed
+  elements (unmapped sites included) equal to a numpy brute force;
   exchanging x <-> y and u <-> w exchanges the solution; translation
   invariance; Landau damping at the kinetic rate with energy conserved.
 """
@@ -250,3 +253,77 @@ def test_landau_damping_4d(v4):
     gamma = np.polyfit(tp, np.log(wp), 1)[0] / 2.0
     assert abs(gamma - wi) <= 0.05 * abs(wi), (gamma, wi)
     assert (max(E) - min(E)) <= 1e-4 * abs(e0)
+
+
+def test_free_streaming_drifts_T_and_H(v4):
+    """G = 0: only the drifts act, and they move the space rows of T and H
+    by t times the velocity rows (the drift of the derivatives, section 2.4
+    per component), on injected random T and H."""
+    ns, nv, L, vmax, dt, n = 16, 8, 4.0, 3.0, 0.25, 8
+    o = v4.Oracle4(ns=ns, nv=nv, L=L, vmax=vmax, ss=4, sv=4, G=0.0, dt=dt,
+                   n_s=0)
+    o.init_conditions(maxwell4(ns, nv, L, vmax, 2 * np.pi / L, 0.0, 0.1))
+    rng = np.random.default_rng(9)
+    el = o.get_elements()
+    E = el.shape[1]
+    el[4:20] += rng.uniform(-0.05, 0.05, (16, E))
+    el[20:60] = rng.uniform(-0.2, 0.2, (40, E))
+    o.set_elements(el)
+    o.step(n)
+    t = n * dt
+    got = o.get_elements()
+    for a in range(2):
+        for b in range(4):
+            want = el[4 + 4 * a + b] + t * el[4 + 4 * (a + 2) + b]
+            assert np.abs(got[4 + 4 * a + b] - want).max() <= 1e-13
+            assert np.array_equal(got[4 + 4 * (a + 2) + b],
+                                  el[4 + 4 * (a + 2) + b])
+        for q in range(10):
+            want = el[20 + 10 * a + q] + t * el[20 + 10 * (a + 2) + q]
+            assert np.abs(got[20 + 10 * a + q] - want).max() <= 1e-13
+            assert np.array_equal(got[20 + 10 * (a + 2) + q],
+                                  el[20 + 10 * (a + 2) + q])
+
+
+def test_validity_window_and_unmapped_sites(v4):
+    """The window |A (P - P_m)| < spacing is strict and per axis: an
+    element is valid inside, not on the edge, not beyond.  With T = I and
+    H = 0 injected and every element moved, the nearest valid element of
+    every site (smallest (d^2, id), x and y periodic, -1 when none) equals a
+    numpy brute force over that definition."""
+    Dm = np.array([2.0, 2.0, 1.0, 1.0])
+    X = np.array([1.0, -1.0, 0.5, 0.25])
+    el = np.zeros(60)
+    el[0:4] = X
+    el[4:20] = np.eye(4).ravel()
+    for off, want in ((0.99, True), (1.0, False), (1.01, False)):
+        for a in range(4):
+            P = X.copy()
+            P[a] += off * Dm[a]
+            assert v4.inverse_map(el, Dm, P, 1e6)[1] == want, (a, off)
+    ns, nv, L, vmax = 16, 8, 4.0, 2.0
+    o = v4.Oracle4(ns=ns, nv=nv, L=L, vmax=vmax, ss=4, sv=4, G=0.0, dt=0.1)
+    o.init_conditions(maxwell4(ns, nv, L, vmax, 2 * np.pi / L, 0.0, 0.1))
+    rng = np.random.default_rng(12)
+    els = o.get_elements()
+    E = els.shape[1]
+    dxs, dus = L / ns, 2 * vmax / nv
+    sp = np.array([4 * dxs, 4 * dxs, 4 * dus, 4 * dus])
+    els[0:2] = np.mod(els[0:2] + rng.uniform(-0.7, 0.7, (2, E)) * sp[:2, None], L)
+    els[2:4] += rng.uniform(-0.7, 0.7, (2, E)) * sp[2:, None]
+    els[2] += 1.5 * sp[2]  # the lowest u rows lose every window
+    els[4:20] = np.eye(4).ravel()[:, None]
+    els[20:60] = 0.0
+    o.set_elements(els)
+    got = o.assignment(True)
+    x = (np.arange(ns) + 0.5) * dxs
+    u = -vmax + (np.arange(nv) + 0.5) * dus
+    W_, U_, Y_, X_ = np.meshgrid(u, u, x, x, indexing="ij")
+    P = np.stack([X_, Y_, U_, W_], -1)                     # (nv, nv, ns, ns, 4)
+    d = P[..., None, :] - els[0:4].T                       # (..., E, 4)
+    d[..., :2] -= L * np.round(d[..., :2] / L)
+    valid = np.all(np.abs(d) < sp, axis=-1)
+    d2 = np.where(valid, np.sum((d / sp) ** 2, axis=-1), np.inf)
+    want = np.where(np.isfinite(d2.min(-1)), np.argmin(d2, axis=-1), -1)
+    assert (want == -1).any() and (want >= 0).any()
+    assert np.array_equal(got, want)
