@@ -355,13 +355,19 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (5x), "
                          "the reference for scaling rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE counters to bytes")
-    ap.add_argument("--leg", choices=["periodic", "four_d"], default=None,
+    ap.add_argument("--leg", choices=["periodic", "four_d", "serve"], default=None,
                     help="run only this extra leg (for profiling) and print "
                          "its JSON")
     args = ap.parse_args()
     if args.leg and args.gpus == 1:
-        res = (periodic_leg(args.steps, args.warmup) if args.leg == "periodic"
-               else four_d_leg(args.steps))
+        if args.leg == "periodic":
+            res = periodic_leg(args.steps, args.warmup)
+        elif args.leg == "four_d":
+            res = four_d_leg(args.steps)
+        else:
+            res = serve_leg(args.serve_requests, args.serve_step_scale, seed=4,
+                            occupancy=args.serve_occupancy, max_active=64,
+                            pool_gb=8.0)
         print(json.dumps(res))
         return
     if args.copy_cal:
