@@ -132,6 +132,56 @@ def variable_step_leg(cfg, f0, steps: int, warmup: int, fixed: dict):
             "simulated_time_per_s": r["diag"]["t"] / r["seconds"]}
 
 
+def emap_leg(cfg, f0, steps: int, warmup: int, fixed: dict,
+             every: int = 10):
+    """Adaptive resampling (end of section 2.3.3) on the same workload: no
+    fixed schedule; every `every` steps E_map of the current elements is
+    computed and the run resamples when it exceeds the value the fixed
+    schedule reaches one step before its first resampling.  Same step
+    count as the fixed run; the resamplings are counted from the engine's
+    per-launch events (second pass)."""
+    import torch
+    import paper_1705_03750_amd as vp
+    p = {k: v for k, v in cfg.params("mixed").items() if k != "precision"}
+    f0t = torch.as_tensor(f0, device="cuda:0")
+    g = vp.VlasovRun(device="cuda:0", precision="mixed", **p)
+    g.init_conditions(f0t)
+    g.step(cfg.n_s - 1)
+    thr = g.diagnostics()["emap"]
+    g.close()
+    pa = dict(p, n_s=0, emap_max=thr, emap_every=every)
+    g = vp.VlasovRun(device="cuda:0", precision="mixed", **pa)
+    g.init_conditions(f0t)
+    if warmup:
+        g.step(warmup)
+    out = {"emap_max": thr, "emap_every": every}
+    for prof in (False, True):
+        g.init_conditions(f0t)
+        g.sync()
+        torch.cuda.synchronize()
+        if prof:
+            g.prof_begin(3 * steps + 16)
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if prof:
+            kern = g.prof_end()
+            n_rm = kern["remap_eval"][1]
+            out.update({"resamplings": n_rm,
+                        "steps_per_resampling": steps / max(1, n_rm),
+                        "fixed_schedule_resamplings": steps // cfg.n_s})
+        else:
+            out.update({"value": cfg.n * cfg.n * steps / (t1 - t0),
+                        "ms_per_step": 1e3 * (t1 - t0) / steps,
+                        "over_fixed_step_time": 1e3 * (t1 - t0) / steps /
+                        fixed["ms_per_step"]})
+    d = g.diagnostics()
+    out.update({"mass": d["mass"], "energy": d["energy"], "emap_end": d["emap"]})
+    g.close()
+    return out
+
+
 def periodic_leg(steps: int, warmup: int):
     """The periodic-x variant at the same size: an electron plasma on a ring
     (two-stream instability, 2048^2, elements every 8th site, dt 0.05,
@@ -355,7 +405,8 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (5x), "
                          "the reference for scaling rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE counters to bytes")
-    ap.add_argument("--leg", choices=["periodic", "four_d", "serve"], default=None,
+    ap.add_argument("--leg", choices=["periodic", "four_d", "serve", "emap"],
+                    default=None,
                     help="run only this extra leg (for profiling) and print "
                          "its JSON")
     args = ap.parse_args()
@@ -364,6 +415,11 @@ def main():
             res = periodic_leg(args.steps, args.warmup)
         elif args.leg == "four_d":
             res = four_d_leg(args.steps)
+        elif args.leg == "emap":
+            import workloads as W
+            cfg, f0 = W.config("c2_halos_2048")
+            fixed = run_gpu("mixed", cfg, f0, args.steps, args.warmup)
+            res = emap_leg(cfg, f0, args.steps, args.warmup, fixed)
         else:
             res = serve_leg(args.serve_requests, args.serve_step_scale, seed=4,
                             occupancy=args.serve_occupancy, max_active=64,
@@ -456,6 +512,13 @@ def main():
                                                  args.warmup, m)
         print(f"[bench] variable step: "
               f"{out['variable_step']['ms_per_step']:.4f} ms/step",
+              file=sys.stderr, flush=True)
+    if args.only is None:
+        out["adaptive_resampling"] = emap_leg(cfg, f0, args.steps,
+                                              args.warmup, m)
+        print(f"[bench] adaptive resampling: "
+              f"{out['adaptive_resampling']['ms_per_step']:.4f} ms/step, "
+              f"{out['adaptive_resampling']['resamplings']} resamplings",
               file=sys.stderr, flush=True)
     if args.only is None:
         out["periodic"] = periodic_leg(args.steps, args.warmup)
