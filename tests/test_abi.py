@@ -92,3 +92,18 @@ def test_vp4_exports_and_validation():
         p = v4.make_params(**bad)
         assert L.vp4_footprint(C.byref(p), C.byref(n)) == v4.VP4Error(
             -1, "").code
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and a message,
+    before touching a device."""
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
