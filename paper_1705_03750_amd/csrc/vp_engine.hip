@@ -567,6 +567,30 @@ int diag_now(vp_ctx *c, double *h, unsigned long long *ovf) {
   return VP_OK;
 }
 
+// E_map of the current state alone, for the adaptive resampling check: the
+// records and lists of the current elements, the E_map reconstruction and
+// the maximum over its workgroups (no field, no energy sums).
+// Synchronises the stream.
+int emap_now(vp_ctx *c, double *emap) {
+  int rc;
+  if ((rc = launch_predict(c, 0, 1))) return rc;
+  rc = c->mixed() ? launch_recon<float, MODE_DIAG>(c, nullptr, nullptr, nullptr)
+                  : launch_recon<double, MODE_DIAG>(c, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  if ((rc = launch_zero_counts(c))) return rc;
+  hipLaunchKernelGGL(k_emap_max, dim3(1), dim3(1024), 0, c->stream,
+                     c->at<double>(c->L.dpart),
+                     (long long)c->L.nwg_x * c->L.nwg_y,
+                     c->at<double>(c->L.dout));
+  VP_LAUNCH_CHECK(c, "k_emap_max");
+  hipError_t e = hipMemcpyAsync(emap, c->at<double>(c->L.dout) + 5,
+                                sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "E_map read");
+  return VP_OK;
+}
+
 // n drift-kick-drift steps.  The kick + corrector of a step and the
 // predictor of the next one share one element pass (k_elem) unless a
 // resampling or the end of the call comes between them, so the elements are
@@ -611,10 +635,9 @@ int run_steps(vp_ctx *c, int n) {
       predicted = false;
       bool remap = remap_due;
       if (check_due) {
-        double h[6];
-        unsigned long long ovf = 0;
-        if ((rc = diag_now(c, h, &ovf))) return rc;
-        remap = h[5] > c->p.emap_max;
+        double emap = 0.0;
+        if ((rc = emap_now(c, &emap))) return rc;
+        remap = emap > c->p.emap_max;
       }
       if (remap && (rc = do_remap(c))) return rc;
     }

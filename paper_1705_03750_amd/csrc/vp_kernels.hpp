@@ -1562,6 +1562,25 @@ __global__ __launch_bounds__(512) void k_remap_eval(
 // Diagnostics (section 3.2): sums of the per-workgroup partials, potential
 // energy from a(i), max |det T - 1|.  out = {mass, e_kin, e_pot, entropy,
 // maxdet}.
+// E_map alone (the adaptive resampling check): the largest of the
+// workgroups' site maxima written by the MODE_DIAG reconstruction, into
+// out[5] as k_diag does.
+__global__ __launch_bounds__(1024) void k_emap_max(
+    const double *__restrict__ dpart, long long nwg, double *__restrict__ out) {
+  __shared__ double sm[1024];
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  for (long long q = tid; q < nwg; q += blockDim.x)
+    m = fmax(m, dpart[3 * q + 2]);
+  sm[tid] = m;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (tid < s) sm[tid] = fmax(sm[tid], sm[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) out[5] = sm[0];
+}
+
 __global__ __launch_bounds__(1024) void k_diag(
     KP p, const double *__restrict__ dpart, long long nwg,
     const double *__restrict__ Ml, const double *__restrict__ acc,
