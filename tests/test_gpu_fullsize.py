@@ -67,6 +67,8 @@ def test_c2_full_size_fp64_remap_cycle(vp, orc):
     o.step(7)
     g.step(7)
     assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(False))
+    # and the remap reconstruction (blended Q_r, cubic spline) of that state
+    assert rel_linf(g.reconstruct_f(1).cpu().numpy(), o.reconstruct_f(1)) <= RTOL
     g.sync()
 
 
