@@ -568,14 +568,15 @@ int diag_now(vp_ctx *c, double *h, unsigned long long *ovf) {
 }
 
 // E_map of the current state alone, for the adaptive resampling check: the
-// records and lists of the current elements, the E_map reconstruction and
-// the maximum over its workgroups (no field, no energy sums).
+// records and lists of the current elements, the reconstruction in its
+// E_map-only mode and the maximum over its workgroups (no field, no energy
+// or entropy sums).
 // Synchronises the stream.
 int emap_now(vp_ctx *c, double *emap) {
   int rc;
   if ((rc = launch_predict(c, 0, 1))) return rc;
-  rc = c->mixed() ? launch_recon<float, MODE_DIAG>(c, nullptr, nullptr, nullptr)
-                  : launch_recon<double, MODE_DIAG>(c, nullptr, nullptr, nullptr);
+  rc = c->mixed() ? launch_recon<float, MODE_EMAP>(c, nullptr, nullptr, nullptr)
+                  : launch_recon<double, MODE_EMAP>(c, nullptr, nullptr, nullptr);
   if (rc) return rc;
   if ((rc = launch_zero_counts(c))) return rc;
   hipLaunchKernelGGL(k_emap_max, dim3(1), dim3(1024), 0, c->stream,

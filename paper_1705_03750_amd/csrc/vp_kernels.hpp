@@ -42,7 +42,8 @@ enum {
   S_HVXV, S_HVVV, NSTATE
 };
 enum { FLAG_NUMERIC = 1, FLAG_WIDE = 2, FLAG_SYNC = 4 };
-enum { MODE_DENSITY = 0, MODE_F = 1, MODE_ASSIGN = 2, MODE_DIAG = 3 };
+enum { MODE_DENSITY = 0, MODE_F = 1, MODE_ASSIGN = 2, MODE_DIAG = 3,
+       MODE_EMAP = 4 };  // MODE_EMAP: the E_map maximum of MODE_DIAG alone
 
 struct KP {
   int nx, nv, sx, sv, mx, mv, E;
@@ -1365,7 +1366,7 @@ __device__ __forceinline__ void recon_tile(
       fout[(size_t)j * p.nx + i] = (FT)0;
     }
     if (MODE == MODE_ASSIGN && live) aout[(size_t)j * p.nx + i] = best;
-    if (MODE == MODE_DIAG && live && best >= 0) {
+    if ((MODE == MODE_DIAG || MODE == MODE_EMAP) && live && best >= 0) {
       // E_map at this site: distance between the nearest element's
       // prediction of Q and those of its valid lattice neighbours
       const int l0 = best / p.mx, k0 = best - l0 * p.mx;
@@ -1386,6 +1387,20 @@ __device__ __forceinline__ void recon_tile(
         em = fmax(em, sqrt(fma(zx, zx, zv * zv)));
       }
     }
+  }
+  if (MODE == MODE_EMAP) {
+    // the workgroup's largest site value, as MODE_DIAG writes it
+    __shared__ double swm[8];
+    const double wm = wave_max(em);
+    if (lane == 0) swm[w] = wm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = swm[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) m = fmax(m, swm[k]);
+      dpart[3 * ((size_t)gy * p.nbx + bx) + 2] = m;
+    }
+    return;
   }
   if (MODE != MODE_DENSITY && MODE != MODE_DIAG) return;
   if (!live) f = 0.0;
@@ -1563,8 +1578,8 @@ __global__ __launch_bounds__(512) void k_remap_eval(
 // energy from a(i), max |det T - 1|.  out = {mass, e_kin, e_pot, entropy,
 // maxdet}.
 // E_map alone (the adaptive resampling check): the largest of the
-// workgroups' site maxima written by the MODE_DIAG reconstruction, into
-// out[5] as k_diag does.
+// workgroups' site maxima written by the MODE_EMAP (or MODE_DIAG)
+// reconstruction, into out[5] as k_diag does.
 __global__ __launch_bounds__(1024) void k_emap_max(
     const double *__restrict__ dpart, long long nwg, double *__restrict__ out) {
   __shared__ double sm[1024];
