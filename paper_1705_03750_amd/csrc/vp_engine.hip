@@ -1155,8 +1155,8 @@ struct vp_server {
   PhaseTable *tabs_dev = nullptr;
   std::vector<char> runs_host;  // RunDesc mirror, one per slot
   PhaseTable *ring = nullptr;   // pinned host [RING][NPH]
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph_lean = nullptr;
+  hipGraphExec_t exec = nullptr, exec_lean = nullptr;
   bool use_graph = false;
   PoolAlloc alloc;
   Slot slot[MAXR];
@@ -1175,19 +1175,24 @@ int srv_fail(vp_server *s, hipError_t e, const char *where) {
   return VP_EDEVICE;
 }
 
+// The launches of one tick.  lean: only the reconstruction, field and kick
+// phases -- a tick in which no run starts, resamples or finishes leaves the
+// other phases' tables empty, and their launches would find nothing to do.
 template <typename FT>
-void launch_tick_kernels(vp_server *s) {
+void launch_tick_kernels(vp_server *s, bool lean) {
   const RunDesc<FT> *runs = reinterpret_cast<const RunDesc<FT> *>(s->runs_dev);
   const PhaseTable *t = s->tabs_dev;
   hipStream_t st = s->stream;
-  hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
-                     t + PH_PRED);
+  if (!lean)
+    hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
+                       t + PH_PRED);
   hipLaunchKernelGGL((kb_recon<FT, MODE_DENSITY>), dim3(GRID_TILE), dim3(512),
                      0, st, runs, t + PH_RECON);
   hipLaunchKernelGGL(kb_field<FT>, dim3(GRID_FIELD), dim3(FIELD_WG), 0, st,
                      runs, t + PH_FIELD);
   hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
                      t + PH_KICK);
+  if (lean) return;
   hipLaunchKernelGGL(kb_elem<FT>, dim3(GRID_ELEM), dim3(256), 0, st, runs,
                      t + PH_RM_PRED);
   hipLaunchKernelGGL(kb_remap<FT>, dim3(GRID_TILE), dim3(512), 0, st, runs,
@@ -1208,11 +1213,11 @@ void launch_tick_kernels(vp_server *s) {
                      t + PH_FIN_ZERO);
 }
 
-void tick_kernels(vp_server *s) {
+void tick_kernels(vp_server *s, bool lean) {
   if (s->precision == VP_MIXED)
-    launch_tick_kernels<float>(s);
+    launch_tick_kernels<float>(s, lean);
   else
-    launch_tick_kernels<double>(s);
+    launch_tick_kernels<double>(s, lean);
 }
 
 template <typename FT>
@@ -1375,20 +1380,24 @@ int vp_server_create(int precision, int max_active, void *dev_pool,
   e = hipMemcpyAsync(s->tabs_dev, s->ring, sizeof(PhaseTable) * NPH,
                      hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  // capture the launch sequence of one tick
-  if (e == hipSuccess &&
-      hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) ==
-          hipSuccess) {
-    tick_kernels(s);
+  // capture the launch sequence of one tick, full and lean
+  for (int lean = 0; lean < 2 && e == hipSuccess; ++lean) {
+    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) !=
+        hipSuccess)
+      break;
+    tick_kernels(s, lean == 1);
     hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
     if (hipStreamEndCapture(s->stream, &g) == hipSuccess && g &&
-        hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0) == hipSuccess) {
-      s->graph = g;
-      s->use_graph = true;
-    } else if (g) {
-      (void)hipGraphDestroy(g);
+        hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) {
+      (lean ? s->graph_lean : s->graph) = g;
+      (lean ? s->exec_lean : s->exec) = x;
+    } else {
+      if (g) (void)hipGraphDestroy(g);
+      break;
     }
   }
+  s->use_graph = s->exec && s->exec_lean;
   (void)hipGetLastError();
   if (e != hipSuccess) {
     g_create_error = std::string("server set-up: ") + hipGetErrorString(e);
@@ -1407,6 +1416,8 @@ int vp_server_destroy(vp_server *s) {
   for (int q = 0; q < MAXR; ++q) delete s->slot[q].c;
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->exec_lean) (void)hipGraphExecDestroy(s->exec_lean);
+  if (s->graph_lean) (void)hipGraphDestroy(s->graph_lean);
   if (s->ring) (void)hipHostFree(s->ring);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
@@ -1594,10 +1605,15 @@ int vp_server_run(vp_server *s, const vp_request *reqs, int n,
     e = hipMemcpyAsync(s->tabs_dev, tab, sizeof(PhaseTable) * NPH,
                        hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) {
+      bool lean = true;
+      for (int ph = 0; ph < NPH && lean; ++ph)
+        if (ph != PH_RECON && ph != PH_FIELD && ph != PH_KICK &&
+            tab[ph].total > 0)
+          lean = false;
       if (s->use_graph) {
-        e = hipGraphLaunch(s->exec, s->stream);
+        e = hipGraphLaunch(lean ? s->exec_lean : s->exec, s->stream);
       } else {
-        tick_kernels(s);
+        tick_kernels(s, lean);
         e = hipGetLastError();
       }
     }
