@@ -190,3 +190,27 @@ def test_tiny_grids_and_single_elements(vp, orc, n, s):
     assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
     assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(True))
     g.sync()
+
+
+def test_ragged_large_grid(vp, orc):
+    """A large grid whose sizes are not multiples of the 8x8 query blocks
+    or the 64-row groups (1020 x 1004 sites, elements every 4th site):
+    25 steps with a resampling at step 20; elements bitwise, f and rho to
+    1e-12, the assignment bit-exact."""
+    n, nv, s = 1020, 1004, 4
+    rng = np.random.default_rng(31)
+    box = (-1.0, 1.0, -1.0, 1.0)
+    f0 = W.finish(W.halo_sum(n, nv, box, rng, 4), box, 1.0)
+    p = dict(nx=n, nv=nv, sx=s, sv=s, dt=5e-4, n_s=20, G=1.0)
+    o = orc.Oracle(**p)
+    o.init_conditions(f0)
+    g = vp.VlasovRun(device="cuda:0", **p)
+    g.init_conditions(f0)
+    print(f"[ragged] {n}x{nv} s={s}", flush=True)
+    o.step(25)
+    g.step(25)
+    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    assert rel_linf(g.density().cpu().numpy(), o.density()) <= RTOL
+    assert np.array_equal(g.assignment().cpu().numpy(), o.assignment(False))
+    g.sync()
