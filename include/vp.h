@@ -216,14 +216,17 @@ int vp_get_assignment(vp_ctx *ctx, int32_t *assign_dev);
 int vp_time(vp_ctx *ctx, double *t, int64_t *step);
 
 /* Profiling hooks.  vp_prof_begin makes every later launch of the engine
- * record a pair of HIP events on the context's stream (at most max_launches
- * launches per kernel kind); vp_prof_end waits for the stream and writes,
+ * record a pair of HIP events on the stream it runs on (the context's, or
+ * for the spline fit after a resampling the context's fit stream; at most
+ * max_launches launches per kernel kind); vp_prof_end waits for both and
+ * writes,
  * for each kernel kind k in [0, VP_PROF_KINDS), the summed elapsed time in
  * milliseconds (ms_host[k]) and the number of timed launches (n_host[k]),
  * then releases the events.  Kinds: 0 element predictor/record, 1 the
- * transport reconstruction with density (k_recon), 2 force, 3 kick, 4 remap
- * evaluation, 5 spline fit, 6 element reset, 7 other.  Returns VP_EDEVICE if
- * events cannot be created. */
+ * transport reconstruction (k_recon; also its E_map-only form in the
+ * adaptive resampling check), 2 force, 3 kick, 4 remap evaluation, 5 spline
+ * fit, 6 element reset, 7 other.  Returns VP_EDEVICE if events cannot be
+ * created. */
 #define VP_PROF_KINDS 8
 int vp_prof_begin(vp_ctx *ctx, int max_launches);
 int vp_prof_end(vp_ctx *ctx, double *ms_host, int64_t *n_host);
