@@ -1132,7 +1132,9 @@ struct Slot {
 
 constexpr int RING = 8;          // host work-table buffers in flight
 constexpr int MAX_INFLIGHT = 3;  // ticks enqueued ahead of the device
-constexpr int GRID_TILE = 2048;  // fixed grids of the batched kernels
+// fixed grids of the batched kernels; the tile grid is larger than the
+// device holds at once, so that the dispatcher balances uneven tiles
+constexpr int GRID_TILE = 8192;
 constexpr int GRID_ELEM = 2048;
 constexpr int GRID_FIT = 1024;
 constexpr int GRID_FIELD = 256;
