@@ -113,6 +113,62 @@ def run_gpu(precision: str, cfg, f0, steps: int, warmup: int, **extra):
     return out
 
 
+def host_io_leg(cfg, f0, steps: int, warmup: int):
+    """The same run with its input and output in host memory: f0 handed
+    over as a host pointer (the library stages it through device memory
+    itself), the steps, then f reconstructed and copied back to host memory.
+    The rate counts the transfers; the device-resident figure (the initial
+    condition already on the device, f left there) is timed beside it with
+    the same clock, so the two differ only by the host hand-over."""
+    import ctypes as C
+    import torch
+    import paper_1705_03750_amd as vp
+    p = cfg.params("mixed")
+    run = vp.VlasovRun(device="cuda:0", **{k: v for k, v in p.items()
+                                           if k != "precision"},
+                       precision="mixed")
+    f0h = np.ascontiguousarray(f0, dtype=np.float64)
+    f0t = torch.as_tensor(f0h, device="cuda:0")
+    run.init_conditions(f0t)
+    run.step(warmup)
+    run.sync()
+    out = {}
+    for where in ("device", "host"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if where == "host":
+            rc = vp.lib().vp_init_conditions(
+                run.h, f0h.ctypes.data_as(C.c_void_p), 0)
+            if rc != 0:
+                raise RuntimeError(f"vp_init_conditions (host): {rc}")
+        else:
+            run.init_conditions(f0t)
+        run.sync()
+        t1 = time.perf_counter()
+        run.step(steps)
+        run.sync()
+        t2 = time.perf_counter()
+        f = run.reconstruct_f()
+        if where == "host":
+            f = f.cpu()
+        run.sync()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out[where] = {"init_ms": 1e3 * (t1 - t0), "steps_ms": 1e3 * (t2 - t1),
+                      "f_out_ms": 1e3 * (t3 - t2),
+                      "value": cfg.n * cfg.n * steps / (t3 - t0)}
+    h, d = out["host"], out["device"]
+    return {"what": f"one {steps}-step run from f0 to f: host f0 (FP64, "
+                    f"{f0h.nbytes >> 20} MiB, pageable) in, f (FP32) out, "
+                    "against the same run device-resident; init includes "
+                    "the spline fit and the element reset",
+            "unit": "site updates/s", "steps": steps,
+            "value": h["value"], "device_resident_value": d["value"],
+            "host": h, "device": d,
+            "transfer_ms": (h["init_ms"] - d["init_ms"]) +
+                           (h["f_out_ms"] - d["f_out_ms"])}
+
+
 def variable_step_leg(cfg, f0, steps: int, warmup: int, fixed: dict):
     """The same workload with the variable step of section 2.4: C_dyn set so
     that the first step is half the nominal dt (which becomes the cap); the
@@ -405,7 +461,8 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (5x), "
                          "the reference for scaling rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE counters to bytes")
-    ap.add_argument("--leg", choices=["periodic", "four_d", "serve", "emap"],
+    ap.add_argument("--leg", choices=["periodic", "four_d", "serve", "emap",
+                                      "host_io"],
                     default=None,
                     help="run only this extra leg (for profiling) and print "
                          "its JSON")
@@ -415,6 +472,10 @@ def main():
             res = periodic_leg(args.steps, args.warmup)
         elif args.leg == "four_d":
             res = four_d_leg(args.steps)
+        elif args.leg == "host_io":
+            import workloads as W
+            cfg, f0 = W.config("c2_halos_2048")
+            res = host_io_leg(cfg, f0, args.steps, args.warmup)
         elif args.leg == "emap":
             import workloads as W
             cfg, f0 = W.config("c2_halos_2048")
@@ -507,6 +568,12 @@ def main():
                        "mixed_over_fp64": m["value"] / f["value"]}
     out["kernels_ms_per_step"] = {
         k: v[0] / args.steps for k, v in m["kernels"].items() if v[1]}
+    if args.only is None:
+        out["host_io"] = host_io_leg(cfg, f0, args.steps, args.warmup)
+        print(f"[bench] host in/out: {out['host_io']['value']:.4e} site "
+              f"updates/s with transfers, "
+              f"{out['host_io']['transfer_ms']:.2f} ms of them",
+              file=sys.stderr, flush=True)
     if args.only is None:
         out["variable_step"] = variable_step_leg(cfg, f0, args.steps,
                                                  args.warmup, m)
