@@ -169,6 +169,42 @@ def host_io_leg(cfg, f0, steps: int, warmup: int):
                            (h["f_out_ms"] - d["f_out_ms"])}
 
 
+def large_grid_leg(plan=(("c3_halos_sheet_8192", 200),
+                         ("c5_halos_cold_16384", 100))):
+    """The two large workloads, mixed and FP64, each timed over a bounded
+    prefix of its run from t = 0 (resamplings included): the 8192^2 halo +
+    sheet workload (s = 8, remap every 50 steps) and the 16384^2 halo + cold
+    workload (s = 16, remap every 20 steps).  Reconstruction rates are the
+    same algorithmic flop and byte counts as the headline's, per launch."""
+    import torch
+    import workloads as W
+    out = {}
+    for name, steps in plan:
+        cfg, f0 = W.config(name)
+        row = {"grid": cfg.n, "element_stride": cfg.s, "n_s": cfg.n_s,
+               "steps": steps}
+        for prec in ("mixed", "fp64"):
+            r = run_gpu(prec, cfg, f0, steps, 10)
+            ms, cnt = r["kernels"]["recon"]
+            avg_s = ms / cnt / 1e3
+            flops = recon_algorithmic_flops(cfg.n)
+            alg = recon_algorithmic_bytes(cfg.n, cfg.s,
+                                          4 if prec == "mixed" else 8)
+            row[prec] = {
+                "value": r["value"], "ms_per_step": r["ms_per_step"],
+                "recon_avg_launch_us": avg_s * 1e6,
+                "recon_alu_frac": flops / avg_s / 1e12 / FP64_PEAK_TFLOPS,
+                "recon_hbm_GBps": alg["total"] / avg_s / 1e9,
+                "kernels_ms_per_step": {k: v[0] / steps for k, v in
+                                        r["kernels"].items() if v[1]}}
+            del r
+            torch.cuda.empty_cache()
+        row["mixed_over_fp64"] = row["mixed"]["value"] / row["fp64"]["value"]
+        out[name] = row
+        del f0
+    return out
+
+
 def variable_step_leg(cfg, f0, steps: int, warmup: int, fixed: dict):
     """The same workload with the variable step of section 2.4: C_dyn set so
     that the first step is half the nominal dt (which becomes the cap); the
@@ -462,7 +498,7 @@ def main():
                          "the reference for scaling rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE counters to bytes")
     ap.add_argument("--leg", choices=["periodic", "four_d", "serve", "emap",
-                                      "host_io"],
+                                      "host_io", "large"],
                     default=None,
                     help="run only this extra leg (for profiling) and print "
                          "its JSON")
@@ -472,6 +508,8 @@ def main():
             res = periodic_leg(args.steps, args.warmup)
         elif args.leg == "four_d":
             res = four_d_leg(args.steps)
+        elif args.leg == "large":
+            res = large_grid_leg()
         elif args.leg == "host_io":
             import workloads as W
             cfg, f0 = W.config("c2_halos_2048")
@@ -592,6 +630,12 @@ def main():
         print(f"[bench] periodic plasma: "
               f"{out['periodic']['ms_per_step']:.4f} ms/step",
               file=sys.stderr, flush=True)
+    if args.only is None:
+        out["large_grids"] = large_grid_leg()
+        for k, v in out["large_grids"].items():
+            print(f"[bench] {k}: mixed {v['mixed']['ms_per_step']:.3f} / "
+                  f"FP64 {v['fp64']['ms_per_step']:.3f} ms/step",
+                  file=sys.stderr, flush=True)
     if args.only is None:
         out["four_d"] = four_d_leg()
         print(f"[bench] 4D: {out['four_d']['ms_per_step']:.3f} ms/step",
