@@ -37,11 +37,18 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash() -> str:
+    """Hash of the engine's code with comments and trailing blanks removed,
+    so that a traffic record stays valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
     for f in ("paper_1705_03750_amd/csrc/vp_kernels.hpp",
               "paper_1705_03750_amd/csrc/vp_engine.hip"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

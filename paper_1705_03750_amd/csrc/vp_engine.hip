@@ -1,14 +1,17 @@
 // vp_engine.hip -- host side of the MI355X engine: workspace carving, step
 // sequencing on the caller's stream, and the C ABI declared in vp.h.
 //
-// Every step runs: k_elem_predict (predictor drift, A = T^-1, query-block
-// lists) -> k_recon (nearest element, inverse map, six-point interpolation,
-// row-group column partials) -> k_field (column sums, cumulative mass,
-// force and derivatives) ->
-// k_elem_kick (TSC, kick, corrector drift); every n_s steps the resampling
-// k_elem_predict -> k_remap_eval -> k_fit_x -> k_fit_v -> k_ghost_x ->
-// k_elem_reset.  Nothing is allocated: all buffers live in the caller's
-// workspace.
+// Every step runs k_recon (nearest element, inverse map, six-point
+// interpolation, row-group column partials) and then the element pass:
+// k_elem_field_coop on grids of at most 2048 columns (column sums,
+// cumulative mass and force, then TSC, kick, corrector drift, the next
+// predictor drift, A = T^-1 and the query-block lists), else k_field and
+// k_field_tail (the field) followed by k_elem.  A run's first step, and
+// the first after a resampling, starts with k_elem (predictor and lists).
+// Every n_s steps the resampling: k_remap_eval, the spline fit (k_fit_x or
+// k_fit_x_cyclic, k_fit_v, ghosts) on a second stream beside the following
+// steps, k_elem_reset.  Nothing is allocated: all buffers live in the
+// caller's workspace.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -381,10 +384,18 @@ int launch_field(vp_ctx *c, const double *in, int from_part, double *rho_out,
     hipLaunchKernelGGL(k_field1, dim3(1), dim3(1024), 0, c->stream, c->k, A);
     VP_LAUNCH_CHECK(c, "k_field1");
   } else {
+    // without periodic x the carries, M_left and the force are spread over
+    // a second launch of the same grid instead of one workgroup's loops
     const int nch = (c->k.nx + FIELD_WG - 1) / FIELD_WG;
+    A.tail = c->k.per ? 0 : 1;
     hipLaunchKernelGGL(k_field, dim3(nch), dim3(FIELD_WG), 0, c->stream, c->k,
                        A);
     VP_LAUNCH_CHECK(c, "k_field");
+    if (A.tail) {
+      hipLaunchKernelGGL(k_field_tail, dim3(nch), dim3(FIELD_WG), 0, c->stream,
+                         c->k, A);
+      VP_LAUNCH_CHECK(c, "k_field_tail");
+    }
   }
   return VP_OK;
 }

@@ -744,7 +744,8 @@ __device__ __forceinline__ double W_kernel(double x) {
 // directly), the sequential prefix and total of each of its chunks; the
 // last workgroup to finish adds the carries and writes M_left and a, a',
 // a'' on the indices [-4, nx + 3] (plus optional copies on [0, nx)).
-__device__ __forceinline__ double Ml_at(const double *Ml, int nx, double Mtot,
+template <typename MP>
+__device__ __forceinline__ double Ml_at(const MP &Ml, int nx, double Mtot,
                                         int i) {
   if (i < 0) return 0.0;
   if (i >= nx) return Mtot;
@@ -790,6 +791,7 @@ struct FieldArgs {
   double *acc;        // a, a', a'' on [-4, nx + 3]
   double *rho_out, *a_out, *da_out, *d2a_out;  // optional
   double *rmx;        // per-workgroup largest rho [nwg] (variable step)
+  int tail;           // k_field publishes only; k_field_tail finishes
 };
 
 __device__ __forceinline__ double ld_coherent(const double *q) {
@@ -800,7 +802,8 @@ __device__ __forceinline__ double ld_coherent(const double *q) {
 
 // Periodic x: M_right - M_left of eq. (acccomp) at site k in [0, nx)
 // minus the uniform background's own, M_tot (2 k + 1) / nx.
-__device__ __forceinline__ double periodic_B(const KP &p, const double *M,
+template <typename MP>
+__device__ __forceinline__ double periodic_B(const KP &p, const MP &M,
                                              double Mtot, int k) {
   const double bg = Mtot * ((double)(2 * k + 1) / (double)p.nx);
   const double Lm = (k >= 1) ? M[k - 1] : 0.0;
@@ -836,7 +839,8 @@ __device__ __forceinline__ double periodic_mean(const KP &p, const double *M,
 // a at any integer site i from M_left: eq. (acccomp) (constant beyond the
 // grid), or with periodic x the force against the background, G (B - mean
 // B) at i mod nx.
-__device__ __forceinline__ double acc_site(const KP &p, const double *M,
+template <typename MP>
+__device__ __forceinline__ double acc_site(const KP &p, const MP &M,
                                            double Mtot, double Bbar, int i) {
   if (p.per) {
     const int k = ((i % p.nx) + p.nx) % p.nx;
@@ -847,7 +851,8 @@ __device__ __forceinline__ double acc_site(const KP &p, const double *M,
 
 // a, a', a'' at table index q (site i = q - 4) from M_left: a' as a centred
 // difference over 2 dx, a'' the three-point second difference.
-__device__ __forceinline__ void acc_from_mass(const KP &p, const double *M,
+template <typename MP>
+__device__ __forceinline__ void acc_from_mass(const KP &p, const MP &M,
                                               double Mtot, double Bbar, int q,
                                               double &a0, double &da,
                                               double &d2a) {
@@ -943,6 +948,12 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
   }
   __syncthreads();
   if (!L.last) return;
+  if (A.tail) {
+    // k_field_tail adds the carries and writes M_left and the force
+    if (tid == 0)
+      __hip_atomic_store(A.fcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   // the last chunk: carries, M_left, force
   for (int k = tid; k < nch; k += FIELD_WG) L.car[k] = ld_coherent(A.ctot + k);
   if (p.clk && tid == 0) {
@@ -988,6 +999,75 @@ __device__ __forceinline__ void field_chunk(const KP &p, const FieldArgs &A,
 __global__ __launch_bounds__(FIELD_WG) void k_field(KP p, FieldArgs A) {
   __shared__ FieldLds L;
   field_chunk(p, A, blockIdx.x, L);
+}
+
+// M_left values of a window of columns held in LDS, indexed by column.
+struct WinM {
+  const double *w;
+  int base;
+  __device__ __forceinline__ double operator[](int i) const {
+    return w[i - base];
+  }
+};
+
+// Second launch of the field for grids without periodic x (after k_field
+// with tail set): workgroup b adds the chunk carries (one sequential chain,
+// the order of the single-workgroup form), writes M_left of its 256 columns
+// and a, a', a'' at the table indices [256 b, 256 b + 256) (the last
+// workgroup also the remaining indices up to nx + 8).  The M_left values
+// its indices read, columns [256 b - 8, 256 b + 272), are formed in LDS from
+// the published chunk prefixes with the same single addition, so no
+// workgroup reads another's output.
+constexpr int TAIL_HALO = 8;
+__global__ __launch_bounds__(FIELD_WG) void k_field_tail(KP p, FieldArgs A) {
+  __shared__ double car[FIELD_CHUNKS + 1];
+  __shared__ double win[FIELD_WG + 3 * TAIL_HALO];
+  const int nx = p.nx, tid = threadIdx.x, b = blockIdx.x;
+  const int nch = (nx + MCHUNK - 1) / MCHUNK;
+  const int n8 = nx + 8;
+  const int q0 = b * FIELD_WG;
+  const int q1 = (b == (int)gridDim.x - 1) ? n8 : min(n8, q0 + FIELD_WG);
+  const int base = q0 - TAIL_HALO;
+  const int nwin = (q1 - q0) + 2 * TAIL_HALO;
+  for (int k = tid; k < nch; k += FIELD_WG) car[k] = A.ctot[k];
+  if (p.clk && b == 0 && tid == 0) {
+    double w = 0.0;
+    const int nwg = (nx + FIELD_WG - 1) / FIELD_WG;
+    for (int k = 0; k < nwg; ++k) w = fmax(w, A.rmx[k]);
+    p.clk[CK_RHO] = w;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double carry = 0.0;
+    for (int k = 0; k < nch; ++k) {
+      const double t = car[k];
+      car[k] = carry;
+      carry = carry + t;
+    }
+  }
+  __syncthreads();
+  for (int u = tid; u < nwin; u += FIELD_WG) {
+    const int i = base + u;
+    if (i >= 0 && i < nx) win[u] = car[i / MCHUNK] + A.Mc[i];
+  }
+  const double Mtot = car[(nx - 1) / MCHUNK] + A.Mc[nx - 1];
+  __syncthreads();
+  const WinM M{win, base};
+  for (int i = q0 + tid; i < min(q0 + FIELD_WG, nx); i += FIELD_WG)
+    A.Ml[i] = M[i];
+  for (int q = q0 + tid; q < q1; q += FIELD_WG) {
+    const int i = q - 4;
+    double a0, da, d2a;
+    acc_from_mass(p, M, Mtot, 0.0, q, a0, da, d2a);
+    A.acc[q] = a0;
+    A.acc[n8 + q] = da;
+    A.acc[2 * n8 + q] = d2a;
+    if (A.a_out && i >= 0 && i < nx) {
+      A.a_out[i] = a0;
+      A.da_out[i] = da;
+      A.d2a_out[i] = d2a;
+    }
+  }
 }
 
 // The same field in one workgroup for grids of at most FIELD1_MAX columns:
