@@ -112,6 +112,27 @@ def test_density_and_poisson(vp, orc):
     g.sync()
 
 
+@pytest.mark.parametrize("nx", [2304, 4100])
+def test_density_and_poisson_wide_grids(vp, orc, nx):
+    """Above 2048 columns the field runs as two launches: column sums and
+    chunk prefixes, then the carries, M_left and a, a', a'' spread over the
+    workgroups (4100 columns leave a ragged last workgroup of 4 columns).
+    Density from a perturbed element state and the force of a given rho,
+    both against the oracle."""
+    p = params(nx, 4, nv=32)
+    o, g = pair(vp, orc, p, halos(nx, 32, seed=nx))
+    el = perturbed(o, 9, amp_x=0.1, amp_t=0.05, amp_h=0.5)
+    o.set_elements(el)
+    g.set_elements(el)
+    print(f"[wide field] nx={nx}", flush=True)
+    r_ref = o.density()
+    assert rel_linf(g.density().cpu().numpy(), r_ref) <= RTOL
+    rho = np.random.default_rng(nx).uniform(0.0, 2.0, nx)
+    for x, y in zip([t.cpu().numpy() for t in g.poisson(rho)], o.poisson(rho)):
+        assert rel_linf(x, y) <= RTOL
+    g.sync()
+
+
 @pytest.mark.parametrize("mode", ["free", "constant", "harmonic",
                                   "anharmonic"])
 def test_element_motion_matches_oracle(vp, orc, mode):
