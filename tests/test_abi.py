@@ -107,3 +107,28 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_traffic_record_follows_the_kernel_code(tmp_path, monkeypatch):
+    """The measured-traffic record is tied to the engine's code: the hash
+    bench.py checks ignores comments and blank lines but changes with any
+    code token."""
+    import shutil
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    rel = ("paper_1705_03750_amd/csrc/vp_kernels.hpp",
+           "paper_1705_03750_amd/csrc/vp_engine.hip")
+    for f in rel:
+        os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
+        shutil.copy(os.path.join(root, f), tmp_path / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    eng = tmp_path / rel[1]
+    text = eng.read_text()
+    eng.write_text("// a new comment\n\n/* and a block\n comment */\n" +
+                   text.replace("\n", "  // trailing\n", 3))
+    assert bench.kernel_source_hash() == h0
+    eng.write_text(text.replace("GRID_TILE = 8192", "GRID_TILE = 4096"))
+    assert bench.kernel_source_hash() != h0
