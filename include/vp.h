@@ -149,6 +149,9 @@ typedef struct vp_diag {
                          one of that element's four lattice neighbours whose
                          validity window holds the site */
   double dt;          /* size of the next step (dt unless c_dyn > 0) */
+  double l1;          /* L1 norm of f, dx dv sum |f| (section 3.2 also
+                         monitors the L1 and L2 norms) */
+  double l2;          /* L2 norm of f, (dx dv sum f^2)^(1/2) */
 } vp_diag;
 
 typedef struct vp_ctx vp_ctx;

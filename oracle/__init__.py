@@ -233,10 +233,10 @@ class Oracle:
         return a, da, d2a
 
     def diagnostics(self) -> dict:
-        out = np.empty(7)
+        out = np.empty(9)
         _check(lib().or_diagnostics(self.h, _dp(out)), "diagnostics")
         keys = ("mass", "e_kin", "e_pot", "energy", "entropy", "max_det_dev",
-                "t")
+                "t", "l1", "l2")
         return dict(zip(keys, out.tolist()))
 
     def emap(self) -> float:

@@ -667,32 +667,17 @@ static double remap_site(const or4_ctx *c, long long q) {
 
 /* ----------------------------------------------------------------- field */
 
-/* rho(i, j) = du dw sum over the velocity sites (u, w), in a fixed order
- * (reading R24, like C9 in 2D): velocity blocks of 4 x 4 sites whose
- * boundaries fall on sites congruent to o = (sv/2) mod 4 modulo 4 (the
- * first and last block of an axis partial when o > 0), w-block outer and
- * u-block inner; each block's values summed w outer, u inner, and the block
- * sums added in that order. */
+/* rho(i, j) = du dw sum over the velocity sites (u, w): for every spatial
+ * site the velocity grid summed sequentially, w outer and u inner, from
+ * (0, 0). */
 static void density(const or4_ctx *c, const double *f, double *rho) {
   int ns = c->ns, nv = c->nv;
-  int o = (c->p.sv / 2) % 4, ob = o > 0;
-  int nb = (nv - 1 - o) / 4 + ob + 1;
   for (int j = 0; j < ns; ++j)
     for (int i = 0; i < ns; ++i) {
       double s = 0.0;
-      for (int bw = 0; bw < nb; ++bw)
-        for (int bu = 0; bu < nb; ++bu) {
-          int l0 = o + 4 * (bw - ob), k0 = o + 4 * (bu - ob);
-          double part = 0.0;
-          for (int l = l0; l < l0 + 4; ++l) {
-            if (l < 0 || l >= nv) continue;
-            for (int k = k0; k < k0 + 4; ++k) {
-              if (k < 0 || k >= nv) continue;
-              part += f[(((size_t)l * nv + k) * ns + j) * ns + i];
-            }
-          }
-          s += part;
-        }
+      for (int l = 0; l < nv; ++l)
+        for (int k = 0; k < nv; ++k)
+          s += f[(((size_t)l * nv + k) * ns + j) * ns + i];
       rho[(size_t)j * ns + i] = (c->du * c->du) * s;
     }
 }

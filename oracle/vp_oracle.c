@@ -698,36 +698,14 @@ static void reconstruct_all(or_ctx *c, double *f, int brute, int32_t *assign) {
 
 /* --------------------------------------------------------------- the field */
 
-/* Column sums S(i) = sum_j f(i, j) in a fixed order (reading C9): rows are
- * taken in groups of 64, the group boundaries falling on rows congruent to
- * o = (sv/2 mod 8) modulo 64, each group made of 8-row strips with
- * boundaries on rows congruent to o modulo 8; a strip is summed
- * sequentially in j, a group adds its strips in order, and the group
- * partials are added sequentially in increasing group order. */
+/* Column sums S(i) = sum_j f(i, j) of the density projection (section
+ * 2.5): every column summed sequentially in increasing j, from row 0. */
 static void column_sums(const or_ctx *c, const double *f, double *S) {
-  int nx = c->nx, nv = c->nv, o = (c->p.sv / 2) % 8;
-  for (int i = 0; i < nx; ++i) S[i] = 0.0;
-  int j = 0;
-  while (j < nv) {
-    int g = (int)floor((double)(j - o) / 64.0);
-    int jend = o + 64 * (g + 1);
-    if (jend > nv) jend = nv;
-    for (int i = 0; i < nx; ++i) {
-      double part = 0.0;
-      int js = j;
-      while (js < jend) {
-        /* an 8-row strip: rows up to the next row = o (mod 8) */
-        int s8 = (int)floor((double)(js - o) / 8.0);
-        int jse = o + 8 * (s8 + 1);
-        if (jse > jend) jse = jend;
-        double strip = 0.0;
-        for (int jj = js; jj < jse; ++jj) strip += f[(size_t)jj * nx + i];
-        part += strip;
-        js = jse;
-      }
-      S[i] += part;
-    }
-    j = jend;
+  int nx = c->nx, nv = c->nv;
+  for (int i = 0; i < nx; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nv; ++j) s += f[(size_t)j * nx + i];
+    S[i] = s;
   }
 }
 
@@ -745,31 +723,20 @@ static double periodic_B(const or_ctx *c, long i) {
   return (bg - c->Ml[i]) - Lm;
 }
 
-/* Cumulative mass M_left(i) = sum_{m <= i} M(m) of section 2.5, taken in
- *  chunks of 64 sites: sequential inside a chunk, the chunk carries added
- * sequentially (reading C9).  M_tot is the last cumulative value (R13). */
+/* Cumulative mass M_left(i) = sum_{m <= i} M(m) of section 2.5 as a
+ * running sum from site 0.  M_tot is the last cumulative value (R13). */
 static void cumulative_mass(or_ctx *c, const double *M) {
   int n = c->nx;
-  double carry = 0.0;
-  for (int c0 = 0; c0 < n; c0 += 64) {
-    int c1 = c0 + 64 < n ? c0 + 64 : n;
-    double p = 0.0;
-    for (int i = c0; i < c1; ++i) {
-      p += M[i];
-      c->Ml[i] = carry + p;
-    }
-    carry = carry + p;
+  double run = 0.0;
+  for (int i = 0; i < n; ++i) {
+    run += M[i];
+    c->Ml[i] = run;
   }
   c->Mtot = c->Ml[n - 1];
   if (c->per) {
-    /* the mean of B(i) (see acc_at), summed in the same 64-site chunks */
+    /* the mean of B(i) (see acc_at), a running sum from site 0 */
     double tot = 0.0;
-    for (int c0 = 0; c0 < n; c0 += 64) {
-      int c1 = c0 + 64 < n ? c0 + 64 : n;
-      double p = 0.0;
-      for (int i = c0; i < c1; ++i) p += periodic_B(c, i);
-      tot = tot + p;
-    }
+    for (int i = 0; i < n; ++i) tot += periodic_B(c, i);
     c->Bbar = tot / (double)n;
   }
 }
@@ -1151,22 +1118,26 @@ static double kval(const ksum *k) { return k->s + k->c; }
 
 /* Diagnostics of section 3.2 at the current time: mass, kinetic and
  * potential energy E = 1/2 int v^2 f - 1/(4G) int (a^2 - G^2 M_tot^2) dx,
- * the Casimir S = -int f log|f|, and max |det T - 1| (eq. detJ).
- * out7 = {mass, E_kin, E_pot, E, S, maxdet, t}. */
-int or_diagnostics(or_ctx *c, double *out7) {
+ * the Casimir S = -int f log|f|, max |det T - 1| (eq. detJ), and the L1
+ * and L2 norms of f that section 3.2 also monitors, int |f| and
+ * (int f^2)^(1/2), every integral a sum over the sites times dx dv.
+ * out9 = {mass, E_kin, E_pot, E, S, maxdet, t, L1, L2}. */
+int or_diagnostics(or_ctx *c, double *out9) {
   if (!c || !c->ready) return OR_ESTATE;
   int rc = prepare_query(c);
   if (rc) return rc;
   reconstruct_all(c, c->f, 0, NULL);
   field_from_f(c, c->f, NULL);
   int nx = c->nx, nv = c->nv;
-  ksum kin = {0, 0}, ent = {0, 0}, pot = {0, 0};
+  ksum kin = {0, 0}, ent = {0, 0}, pot = {0, 0}, l1 = {0, 0}, l2 = {0, 0};
   for (int j = 0; j < nv; ++j) {
     double v = site_v(c, j);
     for (int i = 0; i < nx; ++i) {
       double f = c->f[(size_t)j * nx + i];
       kadd(&kin, v * v * f);
       if (f != 0.0) kadd(&ent, f * log(fabs(f)));
+      kadd(&l1, fabs(f));
+      kadd(&l2, f * f);
     }
   }
   double cell = c->dx * c->dv;
@@ -1198,13 +1169,15 @@ int or_diagnostics(or_ctx *c, double *out7) {
     double dd = fabs(det - 1.0);
     if (dd > maxdet) maxdet = dd;
   }
-  out7[0] = c->Mtot;
-  out7[1] = ekin;
-  out7[2] = epot;
-  out7[3] = ekin + epot;
-  out7[4] = -kval(&ent) * cell;
-  out7[5] = maxdet;
-  out7[6] = c->t;
+  out9[0] = c->Mtot;
+  out9[1] = ekin;
+  out9[2] = epot;
+  out9[3] = ekin + epot;
+  out9[4] = -kval(&ent) * cell;
+  out9[5] = maxdet;
+  out9[6] = c->t;
+  out9[7] = kval(&l1) * cell;
+  out9[8] = sqrt(kval(&l2) * cell);
   return OR_OK;
 }
 

@@ -70,7 +70,7 @@ int or_remap_position(or_ctx *c, int64_t n, const double *P, double *Q);
 int or_density(or_ctx *c, double *rho_out);
 int or_poisson(or_ctx *c, const double *rho, double *a, double *da,
                double *d2a);
-int or_diagnostics(or_ctx *c, double *out7);
+int or_diagnostics(or_ctx *c, double *out9);
 int or_emap(or_ctx *c, double *emap);
 int or_get_elements(or_ctx *c, double *out);
 int or_set_elements(or_ctx *c, const double *in);

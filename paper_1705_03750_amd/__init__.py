@@ -56,7 +56,7 @@ class Diag(C.Structure):
                 ("entropy", C.c_double), ("max_det_dev", C.c_double),
                 ("t", C.c_double), ("step", C.c_int64),
                 ("overflow_blocks", C.c_int64), ("emap", C.c_double),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("l1", C.c_double), ("l2", C.c_double)]
 
 
 class Request(C.Structure):

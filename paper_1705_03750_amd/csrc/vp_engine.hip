@@ -157,7 +157,7 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.clk = take((size_t)CK_DOUBLES * 8);
   L.Ml = take((size_t)k.nx * 8);
   L.acc = take((size_t)3 * (k.nx + 8) * 8);
-  L.dpart = take((size_t)3 * k.nbx * k.ngy * 8);
+  L.dpart = take((size_t)DPS * k.nbx * k.ngy * 8);
   L.dout = take(16 * 8);
   // spline tables: x pivots, v pivots, and (periodic x) z and den
   L.tab = take((size_t)(3 * k.nx + 2 * k.nv + 1) * fb);
@@ -555,8 +555,9 @@ int do_remap(vp_ctx *c) {
 }
 
 // Diagnostics of the current state (positions at the current time): mass,
-// kinetic and potential energy, entropy, max |det T - 1|, E_map into h[6],
-// and the count of overflowed query blocks.  Synchronises the stream.
+// kinetic and potential energy, entropy, max |det T - 1|, E_map, L1, L2
+// into h[8], and the count of overflowed query blocks.  Synchronises the
+// stream.
 int diag_now(vp_ctx *c, double *h, unsigned long long *ovf) {
   int rc;
   if ((rc = launch_predict(c, 0, 1))) return rc;
@@ -568,7 +569,7 @@ int diag_now(vp_ctx *c, double *h, unsigned long long *ovf) {
                      c->at<double>(c->L.Ml), c->at<double>(c->L.acc),
                      c->at<double>(c->L.st), c->at<double>(c->L.dout));
   VP_LAUNCH_CHECK(c, "k_diag");
-  hipError_t e = hipMemcpyAsync(h, c->at<double>(c->L.dout), 6 * sizeof(double),
+  hipError_t e = hipMemcpyAsync(h, c->at<double>(c->L.dout), 8 * sizeof(double),
                                 hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ovf, c->at<unsigned long long>(c->L.ovf), sizeof(*ovf),
@@ -975,7 +976,7 @@ int vp_poisson(vp_ctx *c, const double *rho, double *a, double *da,
 int vp_diagnostics(vp_ctx *c, vp_diag *out) {
   if (!c || !out) return VP_EINVAL;
   if (!c->ready) return VP_ESTATE;
-  double h[6];
+  double h[8];
   unsigned long long ovf = 0;
   int rc = diag_now(c, h, &ovf);
   if (rc) return rc;
@@ -986,6 +987,8 @@ int vp_diagnostics(vp_ctx *c, vp_diag *out) {
   out->entropy = h[3];
   out->max_det_dev = h[4];
   out->emap = h[5];
+  out->l1 = h[6];
+  out->l2 = h[7];
   if ((rc = read_clock(c, &out->dt, &out->t))) return rc;
   out->step = c->step;
   out->overflow_blocks = (int64_t)ovf;

@@ -44,6 +44,9 @@ enum {
 enum { FLAG_NUMERIC = 1, FLAG_WIDE = 2, FLAG_SYNC = 4 };
 enum { MODE_DENSITY = 0, MODE_F = 1, MODE_ASSIGN = 2, MODE_DIAG = 3,
        MODE_EMAP = 4 };  // MODE_EMAP: the E_map maximum of MODE_DIAG alone
+// Per-workgroup diagnostic partials of MODE_DIAG: sum v^2 f, sum f ln|f|,
+// the largest E_map site value, sum |f|, sum f^2.
+enum { DP_KIN = 0, DP_ENT, DP_EMAP, DP_L1, DP_L2, DPS };
 
 struct KP {
   int nx, nv, sx, sv, mx, mv, E;
@@ -1478,7 +1481,7 @@ __device__ __forceinline__ void recon_tile(
       double m = swm[0];
 #pragma unroll
       for (int k = 1; k < 8; ++k) m = fmax(m, swm[k]);
-      dpart[3 * ((size_t)gy * p.nbx + bx) + 2] = m;
+      dpart[DPS * ((size_t)gy * p.nbx + bx) + DP_EMAP] = m;
     }
     return;
   }
@@ -1503,25 +1506,31 @@ __device__ __forceinline__ void recon_tile(
   }
   __syncthreads();
   if (MODE == MODE_DIAG) {
-    // fixed-order tree sums of v^2 f and f ln|f|, and the largest E_map
-    // site value, over the workgroup
-    __shared__ double se[512], sm[512];
+    // fixed-order tree sums of v^2 f, f ln|f|, |f| and f^2, and the largest
+    // E_map site value, over the workgroup
+    __shared__ double se[512], sm[512], s1[512], s2[512];
     se[threadIdx.x] = (f != 0.0) ? f * log(fabs(f)) : 0.0;
     sm[threadIdx.x] = em;
+    s1[threadIdx.x] = fabs(f);
+    s2[threadIdx.x] = f * f;
     __syncthreads();
     for (int s = 256; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
         sk[threadIdx.x] += sk[threadIdx.x + s];
         se[threadIdx.x] += se[threadIdx.x + s];
         sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        s1[threadIdx.x] += s1[threadIdx.x + s];
+        s2[threadIdx.x] += s2[threadIdx.x + s];
       }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
       const size_t wg = (size_t)gy * p.nbx + bx;
-      dpart[3 * wg] = sk[0];
-      dpart[3 * wg + 1] = se[0];
-      dpart[3 * wg + 2] = sm[0];
+      dpart[DPS * wg + DP_KIN] = sk[0];
+      dpart[DPS * wg + DP_ENT] = se[0];
+      dpart[DPS * wg + DP_EMAP] = sm[0];
+      dpart[DPS * wg + DP_L1] = s1[0];
+      dpart[DPS * wg + DP_L2] = s2[0];
     }
   }
   if (w == 0 && lane < 8) {
@@ -1666,7 +1675,7 @@ __global__ __launch_bounds__(1024) void k_emap_max(
   const int tid = threadIdx.x;
   double m = 0.0;
   for (long long q = tid; q < nwg; q += blockDim.x)
-    m = fmax(m, dpart[3 * q + 2]);
+    m = fmax(m, dpart[DPS * q + DP_EMAP]);
   sm[tid] = m;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
@@ -1680,13 +1689,17 @@ __global__ __launch_bounds__(1024) void k_diag(
     KP p, const double *__restrict__ dpart, long long nwg,
     const double *__restrict__ Ml, const double *__restrict__ acc,
     const double *__restrict__ st, double *__restrict__ out) {
-  __shared__ double s0[1024], s1[1024], s2[1024], s3[1024], s4[1024];
+  __shared__ double s0[1024], s1[1024], s2[1024], s3[1024], s4[1024],
+      s5[1024], s6[1024];
   const int tid = threadIdx.x;
-  double kin = 0.0, ent = 0.0, pot = 0.0, mdet = 0.0, emap = 0.0;
+  double kin = 0.0, ent = 0.0, pot = 0.0, mdet = 0.0, emap = 0.0, l1 = 0.0,
+         l2 = 0.0;
   for (long long q = tid; q < nwg; q += blockDim.x) {
-    kin += dpart[3 * q];
-    ent += dpart[3 * q + 1];
-    emap = fmax(emap, dpart[3 * q + 2]);
+    kin += dpart[DPS * q + DP_KIN];
+    ent += dpart[DPS * q + DP_ENT];
+    emap = fmax(emap, dpart[DPS * q + DP_EMAP]);
+    l1 += dpart[DPS * q + DP_L1];
+    l2 += dpart[DPS * q + DP_L2];
   }
   const double Mtot = Ml[p.nx - 1];
   const int n8 = p.nx + 8;
@@ -1719,6 +1732,8 @@ __global__ __launch_bounds__(1024) void k_diag(
   s2[tid] = pot;
   s3[tid] = mdet;
   s4[tid] = emap;
+  s5[tid] = l1;
+  s6[tid] = l2;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
     if (tid < s) {
@@ -1727,6 +1742,8 @@ __global__ __launch_bounds__(1024) void k_diag(
       s2[tid] += s2[tid + s];
       s3[tid] = fmax(s3[tid], s3[tid + s]);
       s4[tid] = fmax(s4[tid], s4[tid + s]);
+      s5[tid] += s5[tid + s];
+      s6[tid] += s6[tid + s];
     }
     __syncthreads();
   }
@@ -1741,6 +1758,8 @@ __global__ __launch_bounds__(1024) void k_diag(
     out[3] = -s1[0] * cell;
     out[4] = s3[0];
     out[5] = s4[0];
+    out[6] = s5[0] * cell;
+    out[7] = sqrt(s6[0] * cell);
   }
 }
 

@@ -1,16 +1,28 @@
 """4D phase-space engine (2D periodic space x 2D velocity, include/vp4.h)
 against the 4D oracle.
 
-The FP64 engine takes the oracle's operations in the oracle's order (the
-density in 4 x 4 velocity blocks, the discrete Fourier transform sums in
-index order with the same twiddles, the same Thomas pivots), so runs agree
-bit for bit: elements, f, the force, the nearest-element ids."""
+The FP64 engine takes the oracle's operations (the discrete Fourier
+transform sums in index order with the same twiddles, the same Thomas
+pivots), so the force of a given density agrees bit for bit.  The density
+itself is summed in the engine's velocity blocks and in the oracle as one
+running sum, so runs agree to that rounding (tests/parity.py): elements by
+their maps, f and rho to 1e-12, the nearest-element ids bit for bit for one
+element state."""
 import math
 
 import numpy as np
 import pytest
 
+from parity import MAP_TOL, RTOL, map_gap4, rel_linf
+
 pytestmark = pytest.mark.gpu
+
+
+def spacings4(p):
+    """Element spacings of the four axes (x, y, u, w)."""
+    dxm = p["L"] / p["ns"] * p["ss"]
+    dum = 2.0 * p["vmax"] / p["nv"] * p["sv"]
+    return [dxm, dxm, dum, dum]
 
 
 @pytest.fixture(scope="module")
@@ -70,15 +82,19 @@ def test_fp64_matches_oracle(v4, o4, ns, nv, ss, sv, G, steps, n_s):
     o.step(steps)
     g.step(steps)
     el = g.get_elements().cpu().numpy()
-    assert np.array_equal(el, o.get_elements())
+    gap = map_gap4(el, o.get_elements(), spacings4(p))
+    assert gap <= MAP_TOL, gap
     assert np.all((el[0:2] >= 0.0) & (el[0:2] < L))
-    assert np.array_equal(g.reconstruct_f().cpu().numpy(), o.reconstruct_f())
-    assert np.array_equal(g.density().cpu().numpy(), o.density())
-    assert np.array_equal(g.assignment().cpu().numpy(), o.assignment())
-    assert np.array_equal(g.reconstruct_f(1).cpu().numpy(), o.reconstruct_f(1))
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    assert rel_linf(g.density().cpu().numpy(), o.density()) <= RTOL
+    assert rel_linf(g.reconstruct_f(1).cpu().numpy(),
+                    o.reconstruct_f(1)) <= RTOL
     d, r = g.diagnostics(), o.diagnostics()
     for k in ("mass", "e_kin", "e_pot", "energy", "entropy", "t"):
         assert abs(d[k] - r[k]) <= 1e-12 * max(1.0, abs(r[k])), k
+    # the nearest element of every site for the oracle's element state
+    g.set_elements(o.get_elements())
+    assert np.array_equal(g.assignment().cpu().numpy(), o.assignment())
     g.sync()
 
 
@@ -148,8 +164,8 @@ def test_validation(v4):
 def test_q4_bench_size(v4, o4):
     """The 4D benchmark workload at its size (64^4 sites, elements every 4th
     site, the launch shapes the benchmark times): one step in FP64, then
-    every element and every site against the oracle, bit for bit; the mixed
-    engine within rel L2 1e-5 of the oracle's f.  The oracle takes about
+    every element and every site against the oracle; the mixed engine
+    within rel L2 1e-5 of the oracle's f.  The oracle takes about
     1.5 minutes here."""
     import time
     import torch
@@ -178,9 +194,10 @@ def test_q4_bench_size(v4, o4):
     o.init_conditions(f0)
     o.step(1)
     print(f"[q4 64^4] oracle stepped at {time.time() - t0:.1f} s", flush=True)
-    assert np.array_equal(out["fp64"][0], o.get_elements())
+    gap = map_gap4(out["fp64"][0], o.get_elements(), spacings4(p))
+    assert gap <= MAP_TOL, gap
     f_ref = o.reconstruct_f()
     print(f"[q4 64^4] oracle f at {time.time() - t0:.1f} s", flush=True)
-    assert np.array_equal(out["fp64"][1], f_ref)
+    assert rel_linf(out["fp64"][1], f_ref) <= RTOL
     fm = out["mixed"][1].astype(np.float64)
     assert np.linalg.norm(fm - f_ref) / np.linalg.norm(f_ref) <= 1e-5

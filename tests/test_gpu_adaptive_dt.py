@@ -4,18 +4,24 @@ against the oracle.
 The step sizes and the time live in a device clock that the element pass
 updates from the density it builds the force from, so no step waits for the
 host.  In FP64 the density maximum, the bound and every step size are the
-oracle's bit for bit, so a variable-step run follows the oracle's trajectory
-exactly through each element-pass variant: the shared field (small grids),
-the field rebuilt per workgroup (few elements, many columns) and the separate
-field kernel (more than 2048 columns)."""
+oracle's to the rounding of the density sums (tests/parity.py), so a
+variable-step run follows the oracle's trajectory through each element-pass
+variant: the shared field (small grids), the field rebuilt per workgroup
+(few elements, many columns) and the separate field kernel (more than 2048
+columns)."""
 import math
 
 import numpy as np
 import pytest
 
 import workloads as W
+from parity import RTOL, TIME_RTOL, assert_elements_close
 
 pytestmark = pytest.mark.gpu
+
+
+def close_t(a, b):
+    return abs(a - b) <= TIME_RTOL * abs(b)
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +70,7 @@ def test_fp64_variable_step_matches_oracle(vp, orc, nx, nv, s, steps, n_s,
     print(f"[{path}] nx={nx} nv={nv} s={s} steps={steps}", flush=True)
     o, g = pair(vp, orc, p, f0)
     d0 = g.diagnostics()
-    assert d0["dt"] == o.dt and d0["t"] == 0.0 and o.dt < cap
+    assert close_t(d0["dt"], o.dt) and d0["t"] == 0.0 and o.dt < cap
     # a second engine run takes the steps one call at a time: the element
     # pass then ends each step without the next predictor
     g1 = vp.VlasovRun(device="cuda:0", **p)
@@ -78,14 +84,14 @@ def test_fp64_variable_step_matches_oracle(vp, orc, nx, nv, s, steps, n_s,
     g.step(steps)
     for run in (g, g1):
         d = run.diagnostics()
-        assert d["t"] == o.t and d["dt"] == o.dt and d["step"] == steps
+        assert close_t(d["t"], o.t) and close_t(d["dt"], o.dt)
+        assert d["step"] == steps
         t, st = run.time()
-        assert t == o.t and st == steps
-        assert np.array_equal(run.get_elements().cpu().numpy(),
-                              o.get_elements())
+        assert t == d["t"] and st == steps
+        assert_elements_close(run.get_elements().cpu().numpy(), o)
     f_ref = o.reconstruct_f()
     f = g.reconstruct_f().cpu().numpy()
-    assert np.abs(f - f_ref).max() <= 1e-12 * np.abs(f_ref).max()
+    assert np.abs(f - f_ref).max() <= RTOL * np.abs(f_ref).max()
     g.sync()
     g1.sync()
 
@@ -108,9 +114,9 @@ def test_variable_step_with_emap_resampling(vp, orc):
     free.init_conditions(f0)
     free.step(24)
     assert not np.array_equal(free.get_elements(), o.get_elements())
-    assert np.array_equal(g.get_elements().cpu().numpy(), o.get_elements())
+    assert_elements_close(g.get_elements().cpu().numpy(), o)
     d = g.diagnostics()
-    assert d["t"] == o.t and d["dt"] == o.dt
+    assert close_t(d["t"], o.t) and close_t(d["dt"], o.dt)
     g.sync()
 
 

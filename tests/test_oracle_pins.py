@@ -639,6 +639,34 @@ def test_uniform_slab_potential_energy(orc):
     assert abs(d["e_kin"] - 0.5 * M * 0.01) < 1e-3 * 0.5 * M * 0.01
 
 
+def test_casimir_entropy_and_norms_of_a_gaussian(orc):
+    """Casimir S = -int f ln|f|, L1 = int |f| and L2 = (int f^2)^(1/2) of
+    section 3.2 for f = A exp(-(x^2 + v^2) / (2 sigma^2)), mass
+    M = 2 pi sigma^2 A: S = M (1 - ln A), L1 = M, L2 = A sigma sqrt(pi)
+    (closed forms of the integrals; with sigma = 0.12 the Gaussian's mass
+    beyond the box edge is ~1e-15, and the site sums of a Gaussian resolved
+    by 15 sites per sigma equal its integral to far below that).  For -f, S changes sign and
+    the norms do not, which pins the |f| in the logarithm."""
+    n, sig = 256, 0.12
+    x = W.site_coords(n, -1, 1)
+    r2 = x[None, :] ** 2 + x[:, None] ** 2
+    for A in (5.0, 0.2):
+        g = A * np.exp(-r2 / (2 * sig * sig))
+        M = 2 * math.pi * sig * sig * A
+        S = M * (1.0 - math.log(A))
+        L2 = A * sig * math.sqrt(math.pi)
+        for sign in (1.0, -1.0):
+            o = orc.Oracle(**box_params(n, 4))
+            o.init_conditions(sign * g)
+            d = o.diagnostics()
+            assert abs(d["mass"] - sign * M) < 1e-9 * M
+            assert abs(d["entropy"] - sign * S) < 1e-9 * abs(S), (A, sign)
+            assert abs(d["l1"] - M) < 1e-9 * M
+            assert abs(d["l2"] - L2) < 1e-9 * L2
+            assert abs(d["e_kin"] - sign * 0.5 * M * sig * sig) < \
+                1e-9 * M * sig * sig
+
+
 # ------------------------------------------------------ paper's numbers
 def test_paper_printed_values(orc):
     """Numbers printed in the paper (tests/golden/paper_values.json)."""
