@@ -187,9 +187,15 @@ int vp_step(vp_ctx *ctx, int nsteps);
  * cubic spline becomes F_ini; new isotropic elements. */
 int vp_remap(vp_ctx *ctx);
 
-/* f at the current time on every site, scheme VP_SCHEME_TRANSPORT or
- * VP_SCHEME_REMAP; state unchanged.  f_out_dev: nv*nx device values, double
- * (float in VP_MIXED). */
+/* f at the current time on every site; state unchanged.  Scheme
+ * VP_SCHEME_TRANSPORT: the nearest element's second-order inverse map
+ * (section 2.1, eq. QofP) and the six-point interpolation of F_ini (section
+ * 2.2.1, eq. int1); VP_SCHEME_REMAP: the W-weighted blend Q_r of the
+ * neighbours' predictions (section 2.3.2) and the cubic B-spline of F_ini
+ * (section 2.2.2), the values a resampling would store.  f_out_dev: nv*nx
+ * device values (caller owned), row-major, double (float in VP_MIXED).
+ * EINVAL for a bad scheme or null pointer, ESTATE before
+ * vp_init_conditions.  Asynchronous. */
 int vp_reconstruct_f(vp_ctx *ctx, int scheme, void *f_out_dev);
 
 /* Projected density rho(x_i) = dv sum_j f(i, j) of the transport
