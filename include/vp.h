@@ -210,6 +210,27 @@ int vp_density(vp_ctx *ctx, double *rho_out_dev);
 int vp_poisson(vp_ctx *ctx, const double *rho_dev, double *a_dev,
                double *da_dev, double *d2a_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the force
+ * of vp_poisson for a density without a run context or a workspace.
+ * p: the run parameters (only nx, x_min, x_max, G and bc enter; the whole
+ * struct must pass the checks of vp_create).  rho_dev: nx device doubles
+ * (read); a_dev, da_dev, d2a_dev: nx device doubles each (written, caller
+ * owned).  Work is enqueued on hip_stream (NULL: the null stream) and the
+ * call returns without waiting.  The intermediate sums live in one
+ * library-owned device array of VP_POISSON_STATIC_BYTES per GPU, taken when
+ * the library is loaded and held until the process ends; every call on a
+ * GPU shares that array and leaves the last call's contents in it, so calls
+ * that overlap on one GPU (two streams, two host threads) race.  Results
+ * are bit for bit those of vp_poisson.  Errors: VP_EINVAL for invalid
+ * parameters, a null pointer or nx > VP_POISSON_STATIC_MAX_NX; VP_EDEVICE
+ * on a HIP error; text of either in vp_last_error(NULL). */
+#define VP_POISSON_STATIC_MAX_NX 16384
+#define VP_POISSON_STATIC_BYTES ((size_t)8 * (5 * 16384 + 24 + 2 * 2048 + 32))
+int vp_poisson_static(const vp_params *p, const double *rho_dev,
+                      double *a_dev, double *da_dev, double *d2a_dev,
+                      void *hip_stream);
+
 /* Diagnostics of section 3.2 at the current time (synchronises). */
 int vp_diagnostics(vp_ctx *ctx, vp_diag *out_host);
 
@@ -302,8 +323,8 @@ const char *vp_server_last_error(vp_server *srv);
 /* Wait for the stream; report a pending device-side VP_ENUMERIC. */
 int vp_sync(vp_ctx *ctx);
 
-/* Text of the last error on this context (or of the last failed create when
- * ctx is NULL). */
+/* Text of the last error on this context (or, when ctx is NULL, of the
+ * last failed vp_create or vp_poisson_static on this host thread). */
 const char *vp_last_error(vp_ctx *ctx);
 
 #ifdef __cplusplus

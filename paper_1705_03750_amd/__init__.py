@@ -27,7 +27,7 @@ BETA_PAPER = 0.5 * (1.0 - math.sqrt(3.0) / 2.0)
 EXPORTS = (
     "vp_footprint", "vp_create", "vp_destroy", "vp_init_conditions",
     "vp_step", "vp_remap", "vp_reconstruct_f", "vp_density", "vp_poisson",
-    "vp_diagnostics", "vp_get_elements", "vp_set_elements",
+    "vp_poisson_static", "vp_diagnostics", "vp_get_elements", "vp_set_elements",
     "vp_get_assignment", "vp_time", "vp_sync", "vp_last_error",
     "vp_prof_begin", "vp_prof_end", "vp_server_footprint", "vp_server_create",
     "vp_server_run", "vp_server_destroy", "vp_server_last_error",
@@ -108,6 +108,7 @@ def lib():
             "vp_reconstruct_f": [vp, C.c_int, vp],
             "vp_density": [vp, vp],
             "vp_poisson": [vp, vp, vp, vp, vp],
+            "vp_poisson_static": [pp, vp, vp, vp, vp, vp],
             "vp_diagnostics": [vp, C.POINTER(Diag)],
             "vp_get_elements": [vp, vp],
             "vp_set_elements": [vp, vp],
@@ -159,6 +160,30 @@ def footprint(**kw) -> int:
     if rc:
         raise VPError(rc, "invalid parameters")
     return int(n.value)
+
+
+def poisson_static(rho, stream=None, **kw):
+    """a, a', a'' of a density (nx float64 values on a HIP device) through
+    vp_poisson_static: no run context, no workspace, nothing allocated by
+    the library (outputs are new torch tensors here).  Keyword parameters as
+    VlasovRun (nx taken from rho)."""
+    import torch
+    r = rho if isinstance(rho, torch.Tensor) else torch.as_tensor(rho)
+    if r.device.type != "cuda":
+        raise ValueError("rho must be a device tensor")
+    r = r.to(torch.float64).contiguous()
+    kw = dict(kw)
+    kw["nx"] = int(r.numel())
+    kw.setdefault("sx", 4 if kw["nx"] % 8 else 8)
+    p = make_params(**kw)
+    outs = [torch.empty_like(r) for _ in range(3)]
+    st = stream if stream is not None else torch.cuda.current_stream(r.device)
+    rc = lib().vp_poisson_static(C.byref(p), C.c_void_p(r.data_ptr()),
+                                 *[C.c_void_p(o.data_ptr()) for o in outs],
+                                 C.c_void_p(st.cuda_stream))
+    if rc:
+        raise VPError(rc, (lib().vp_last_error(None) or b"").decode())
+    return tuple(outs)
 
 
 class VlasovRun:

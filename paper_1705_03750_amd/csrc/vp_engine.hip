@@ -28,6 +28,7 @@
 
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <thread>
 
 using namespace vpk;
@@ -363,6 +364,28 @@ int launch_recon(vp_ctx *c, void *fout, int *aout, double *rho_out) {
   return VP_OK;
 }
 
+// The field launches for a filled FieldArgs: one workgroup up to FIELD1_MAX
+// columns, else the column-chunk kernel and, without periodic x, the
+// carries, M_left and the force spread over a second launch.  Returns the
+// launch status (where names the failing kernel).
+hipError_t field_launches(const KP &k, FieldArgs &A, hipStream_t s,
+                          const char **where) {
+  if (k.nx <= FIELD1_MAX) {
+    *where = "k_field1";
+    hipLaunchKernelGGL(k_field1, dim3(1), dim3(1024), 0, s, k, A);
+    return hipGetLastError();
+  }
+  const int nch = (k.nx + FIELD_WG - 1) / FIELD_WG;
+  A.tail = k.per ? 0 : 1;
+  *where = "k_field";
+  hipLaunchKernelGGL(k_field, dim3(nch), dim3(FIELD_WG), 0, s, k, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !A.tail) return e;
+  *where = "k_field_tail";
+  hipLaunchKernelGGL(k_field_tail, dim3(nch), dim3(FIELD_WG), 0, s, k, A);
+  return hipGetLastError();
+}
+
 int launch_field(vp_ctx *c, const double *in, int from_part, double *rho_out,
                  double *a_out, double *da_out, double *d2a_out) {
   ProfScope ps(c, PK_FIELD);
@@ -380,23 +403,9 @@ int launch_field(vp_ctx *c, const double *in, int from_part, double *rho_out,
   A.da_out = da_out;
   A.d2a_out = d2a_out;
   A.rmx = c->at<double>(c->L.rmx);
-  if (c->k.nx <= FIELD1_MAX) {
-    hipLaunchKernelGGL(k_field1, dim3(1), dim3(1024), 0, c->stream, c->k, A);
-    VP_LAUNCH_CHECK(c, "k_field1");
-  } else {
-    // without periodic x the carries, M_left and the force are spread over
-    // a second launch of the same grid instead of one workgroup's loops
-    const int nch = (c->k.nx + FIELD_WG - 1) / FIELD_WG;
-    A.tail = c->k.per ? 0 : 1;
-    hipLaunchKernelGGL(k_field, dim3(nch), dim3(FIELD_WG), 0, c->stream, c->k,
-                       A);
-    VP_LAUNCH_CHECK(c, "k_field");
-    if (A.tail) {
-      hipLaunchKernelGGL(k_field_tail, dim3(nch), dim3(FIELD_WG), 0, c->stream,
-                         c->k, A);
-      VP_LAUNCH_CHECK(c, "k_field_tail");
-    }
-  }
+  const char *where = "field";
+  const hipError_t e = field_launches(c->k, A, c->stream, &where);
+  if (e != hipSuccess) return dev_fail(c, e, where);
   return VP_OK;
 }
 
@@ -1088,6 +1097,105 @@ const char *vp_last_error(vp_ctx *c) {
 }
 
 }  // extern "C"
+
+// ================================ vp_poisson without a context or workspace
+//
+// The field's intermediate buffers (chunk prefixes, chunk totals and
+// maxima, M_left, the force table on [-4, nx + 3], the finished-chunk
+// counter) in one file-scope device array.  In host code `scratch` names a
+// host-side stand-in, not the device memory: its device address is taken
+// with hipGetSymbolAddress once per device (each GPU holds its own copy)
+// and only that address is handed to kernels.
+namespace {
+constexpr size_t SP_NX = VP_POISSON_STATIC_MAX_NX;
+constexpr size_t SP_MC = 0;                            // [SP_NX]
+constexpr size_t SP_ML = SP_MC + SP_NX;                // [SP_NX]
+constexpr size_t SP_ACC = SP_ML + SP_NX;               // [3 (SP_NX + 8)]
+constexpr size_t SP_CTOT = SP_ACC + 3 * (SP_NX + 8);   // [FIELD_CHUNKS]
+constexpr size_t SP_RMX = SP_CTOT + FIELD_CHUNKS;      // [FIELD_CHUNKS]
+constexpr size_t SP_CNT = SP_RMX + FIELD_CHUNKS;       // int counter (256 B)
+constexpr size_t SP_DOUBLES = SP_CNT + 32;
+static_assert(SP_DOUBLES * sizeof(double) == VP_POISSON_STATIC_BYTES,
+              "VP_POISSON_STATIC_BYTES");
+static_assert(SP_NX <= (size_t)FIELD_CHUNKS * MCHUNK, "chunk tables");
+}  // namespace
+
+static __device__ __align__(256) double scratch[SP_DOUBLES];
+
+namespace {
+constexpr int SP_MAX_DEVICES = 64;
+std::mutex g_sp_mu;
+double *g_sp_ptr[SP_MAX_DEVICES] = {};  // device address of `scratch`
+
+// Device address of the scratch array on the current device, looked up
+// on the first call made with that device current.
+int static_scratch(double **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return VP_EDEVICE;
+  }
+  if (dev < 0 || dev >= SP_MAX_DEVICES) {
+    g_create_error = "device index beyond the static scratch table";
+    return VP_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_sp_mu);
+  if (!g_sp_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      g_create_error = std::string("hipGetSymbolAddress: ") +
+                       hipGetErrorString(e);
+      return VP_EDEVICE;
+    }
+    g_sp_ptr[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_sp_ptr[dev];
+  return VP_OK;
+}
+}  // namespace
+
+extern "C" int vp_poisson_static(const vp_params *p, const double *rho,
+                                 double *a, double *da, double *d2a,
+                                 void *hip_stream) {
+  if (!params_ok(p) || !rho || !a || !da || !d2a) {
+    g_create_error = "invalid parameters or null pointer";
+    return VP_EINVAL;
+  }
+  if ((size_t)p->nx > SP_NX) {
+    g_create_error = "nx above VP_POISSON_STATIC_MAX_NX";
+    return VP_EINVAL;
+  }
+  double *sp = nullptr;
+  if (const int rc = static_scratch(&sp)) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const KP k = make_kp(p);
+  FieldArgs A{};
+  A.in = rho;
+  A.ngy = 0;
+  A.in_is_rho = 1;
+  A.Mc = sp + SP_MC;
+  A.ctot = sp + SP_CTOT;
+  A.fcnt = reinterpret_cast<int *>(sp + SP_CNT);
+  A.Ml = sp + SP_ML;
+  A.acc = sp + SP_ACC;
+  A.rmx = sp + SP_RMX;
+  A.a_out = a;
+  A.da_out = da;
+  A.d2a_out = d2a;
+  // the finished-chunk counter starts at zero (a fill kernel, so that the
+  // call can be captured into a graph)
+  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, A.fcnt, 1LL, 0);
+  hipError_t e = hipGetLastError();
+  const char *where = "k_fill";
+  if (e == hipSuccess) e = field_launches(k, A, s, &where);
+  if (e != hipSuccess) {
+    g_create_error = std::string(where) + ": " + hipGetErrorString(e);
+    return VP_EDEVICE;
+  }
+  return VP_OK;
+}
 
 // ================================================================ serving
 

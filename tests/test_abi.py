@@ -132,3 +132,18 @@ def test_traffic_record_follows_the_kernel_code(tmp_path, monkeypatch):
     assert bench.kernel_source_hash() == h0
     eng.write_text(text.replace("GRID_TILE = 8192", "GRID_TILE = 4096"))
     assert bench.kernel_source_hash() != h0
+
+
+def test_poisson_static_validates_on_the_host(vp):
+    """vp_poisson_static's argument checks come before any device work:
+    null pointers and nx above VP_POISSON_STATIC_MAX_NX give EINVAL with a
+    message in vp_last_error(NULL)."""
+    L = vp.lib()
+    p = vp.make_params(nx=64, sx=8, dt=1e-3)
+    assert L.vp_poisson_static(C.byref(p), None, None, None, None,
+                               None) == vp.EINVAL
+    big = vp.make_params(nx=16384 + 8, sx=8, dt=1e-3)
+    fake = C.c_void_p(256)  # never dereferenced: rejected first
+    assert L.vp_poisson_static(C.byref(big), fake, fake, fake, fake,
+                               None) == vp.EINVAL
+    assert b"VP_POISSON_STATIC_MAX_NX" in L.vp_last_error(None)
