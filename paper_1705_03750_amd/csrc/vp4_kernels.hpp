@@ -503,17 +503,33 @@ __device__ __forceinline__ FT int15(const KP &p, const FT *__restrict__ F,
   return f;
 }
 
+// Cubic B-spline weights.  Double precision: each times the rounded 1/6.
+// Single precision: six times the weights, the 1/6^4 of the four axes
+// applied once to the sum (two-float constant), because float(1/6) is 3e-8
+// too large and that shared rounding would scale every resampled value by
+// 1 + 1.2e-7 at each resampling.
 template <typename FT>
 __device__ __forceinline__ void bspw(double ud, FT b[4]) {
   const FT u = (FT)ud;
-  const FT sixth = (FT)(1.0 / 6.0);
   const FT t = (FT)1 - u;
   const FT u2 = u * u, u3 = u2 * u;
-  b[0] = ((t * t) * t) * sixth;
-  b[1] = (((FT)3 * u3 - (FT)6 * u2) + (FT)4) * sixth;
-  b[2] = ((((FT)-3 * u3 + (FT)3 * u2) + (FT)3 * u) + (FT)1) * sixth;
-  b[3] = u3 * sixth;
+  if constexpr (sizeof(FT) == 8) {
+    const FT sixth = (FT)(1.0 / 6.0);
+    b[0] = ((t * t) * t) * sixth;
+    b[1] = (((FT)3 * u3 - (FT)6 * u2) + (FT)4) * sixth;
+    b[2] = ((((FT)-3 * u3 + (FT)3 * u2) + (FT)3 * u) + (FT)1) * sixth;
+    b[3] = u3 * sixth;
+  } else {
+    b[0] = (t * t) * t;
+    b[1] = ((FT)3 * u3 - (FT)6 * u2) + (FT)4;
+    b[2] = (((FT)-3 * u3 + (FT)3 * u2) + (FT)3 * u) + (FT)1;
+    b[3] = u3;
+  }
 }
+
+constexpr float INV1296_HI = (float)(1.0 / 1296.0);
+constexpr float INV1296_LO =
+    (float)(1.0 / 1296.0 - (double)(float)(1.0 / 1296.0));
 
 // Tensor cubic B-spline (x, y periodic, clamped to [-12, ns + 11]; u, w on
 // [0, nv - 1] with mirror ghosts c(-1) = c(1), c(n) = c(n - 2); 0 outside).
@@ -566,6 +582,7 @@ __device__ __forceinline__ FT spline4(const KP &p, const FT *__restrict__ C,
     }
     f = (l == 0) ? w[3][0] * fu : fma(w[3][l], fu, f);
   }
+  if constexpr (sizeof(FT) == 4) f = fmaf(f, INV1296_HI, f * INV1296_LO);
   return f;
 }
 

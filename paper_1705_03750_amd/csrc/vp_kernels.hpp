@@ -682,17 +682,36 @@ __device__ __forceinline__ FT int1(const KP &p, const FT *__restrict__ F,
   return f;
 }
 
+// Cubic B-spline weights at offset u in [0, 1].  In double precision the
+// four weights, each times the rounded 1/6.  In single precision six times
+// the weights: float(1/6) exceeds 1/6 by 3e-8, and that one rounding,
+// shared by every weight of every site, would scale every resampled value
+// (and the mass) by 1 + 6e-8 at each resampling; spline_eval applies the
+// 1/36 of the two axes once instead, split into two floats so that the
+// product rounds as the exact quotient would.
 template <typename FT>
 __device__ __forceinline__ void bspline_w(double ud, FT b[4]) {
   const FT u = (FT)ud;
-  const FT sixth = (FT)(1.0 / 6.0);
   const FT t = (FT)1 - u;
   const FT u2 = u * u, u3 = u2 * u;
-  b[0] = ((t * t) * t) * sixth;
-  b[1] = (((FT)3 * u3 - (FT)6 * u2) + (FT)4) * sixth;
-  b[2] = ((((FT)-3 * u3 + (FT)3 * u2) + (FT)3 * u) + (FT)1) * sixth;
-  b[3] = u3 * sixth;
+  if constexpr (sizeof(FT) == 8) {
+    const FT sixth = (FT)(1.0 / 6.0);
+    b[0] = ((t * t) * t) * sixth;
+    b[1] = (((FT)3 * u3 - (FT)6 * u2) + (FT)4) * sixth;
+    b[2] = ((((FT)-3 * u3 + (FT)3 * u2) + (FT)3 * u) + (FT)1) * sixth;
+    b[3] = u3 * sixth;
+  } else {
+    b[0] = (t * t) * t;
+    b[1] = ((FT)3 * u3 - (FT)6 * u2) + (FT)4;
+    b[2] = (((FT)-3 * u3 + (FT)3 * u2) + (FT)3 * u) + (FT)1;
+    b[3] = u3;
+  }
 }
+
+// 1/36 as the sum of two floats (the normalisation of single-precision
+// tensor weights in two axes).
+constexpr float INV36_HI = (float)(1.0 / 36.0);
+constexpr float INV36_LO = (float)(1.0 / 36.0 - (double)(float)(1.0 / 36.0));
 
 // Cubic B-spline value (section 2.2.2) from coefficients C (padded, with
 // mirror ghosts one site deep) at index-space position (sx, sv).
@@ -721,6 +740,7 @@ __device__ __forceinline__ FT spline_eval(const KP &p, const FT *__restrict__ C,
     row = fma(bx[3], cr[3], row);
     f = (b == 0) ? bv[0] * row : fma(bv[b], row, f);
   }
+  if constexpr (sizeof(FT) == 4) f = fmaf(f, INV36_HI, f * INV36_LO);
   return f;
 }
 
