@@ -8,7 +8,9 @@ The binding fails loudly when libvp.so is missing; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 import math
 import os
 
@@ -86,6 +88,22 @@ class VPError(RuntimeError):
 
 
 _lib = None
+
+# Every live run and server, closed by an exit handler: the library's HIP
+# streams, events and pinned buffers are released while the runtime is
+# still whole, not by finalisers during interpreter teardown.
+_live = weakref.WeakSet()
+
+
+def _close_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
 
 
 def lib():
@@ -219,6 +237,7 @@ class VlasovRun:
                                   C.byref(h)), None)
         self.h = h
         self._keep = []
+        _live.add(self)
 
     # ----------------------------------------------------------------
     def _chk(self, rc, h):
@@ -347,6 +366,7 @@ class Server:
         if rc:
             raise VPError(rc, lib().vp_server_last_error(None).decode())
         self.h = h
+        _live.add(self)
 
     def run(self, requests):
         """requests: list of dicts with params (make_params kwargs), f0

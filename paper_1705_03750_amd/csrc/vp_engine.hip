@@ -892,6 +892,10 @@ int vp_destroy(vp_ctx *c) {
   if (!c) return VP_EINVAL;
   const int rc = join_fit(c);
   const hipError_t e = hipStreamSynchronize(c->stream);
+  // profiling events of a vp_prof_begin without its vp_prof_end
+  for (int k = 0; k < PK_N; ++k)
+    for (auto &ev : c->ev[k])
+      if (ev) (void)hipEventDestroy(ev);
   if (c->aux) {
     (void)hipEventDestroy(c->ev_eval);
     (void)hipEventDestroy(c->ev_fit);

@@ -7,6 +7,8 @@ import ctypes as C
 import math
 import os
 
+from . import _live
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB4_PATH = os.path.join(_HERE, "libvp4.so")
 
@@ -112,6 +114,7 @@ class VlasovRun4:
                                    C.byref(h)), None)
         self.h = h
         self._keep = []
+        _live.add(self)
 
     def _chk(self, rc, h):
         if rc != 0:
