@@ -284,11 +284,12 @@ int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
   k.par ^= 1;  // completes the previous step (see launch_elem)
   ProfScope ps(c, PK_KICK);
   const long long nbz = c->L.nb;
+  const int nch = (k.nx + MCHUNK - 1) / MCHUNK;
+  // one workgroup per element patch, at least one per field chunk
+  const int grid = std::max(elem_patches(k.mx, k.mv), nch);
   const long long n =
       std::max<long long>(k.E, std::min<long long>(nbz, 1 << 22));
-  const int grid = (int)grid_for(n, ELEMC_WG);
-  const int nch = (k.nx + MCHUNK - 1) / MCHUNK;
-  if (grid <= c->coop_grid && grid >= nch) {
+  if (grid <= c->coop_grid) {
     int *fsync = c->at<int>(c->L.fsync);
     if (c->fsync_target + nch > (1 << 30)) {
       hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(256), 0, c->stream,

@@ -236,6 +236,19 @@ struct AccTable {
   }
 };
 
+// TSC cell of a position (section 2.5): u = (x - x_min)/dx - 1/2, clamped
+// to [-3, nx + 2] (the force is constant beyond the grid, and a NaN
+// position lands on -3), its nearest site floor(u + 1/2) (returned) and the
+// offset w of u from it.
+__device__ __forceinline__ double tsc_cell(const KP &p, double x, double &w) {
+  double u = (x - p.x_min) * p.inv_dx - 0.5;
+  if (!(u >= -3.0)) u = -3.0;
+  if (u > (double)p.nx + 2.0) u = (double)p.nx + 2.0;
+  const double fi = floor(u + 0.5);
+  w = u - fi;
+  return fi;
+}
+
 template <typename Acc>
 __device__ __forceinline__ void elem_kick(const KP &p, const Acc &acc,
                                           ElemState &s) {
@@ -245,11 +258,8 @@ __device__ __forceinline__ void elem_kick(const KP &p, const Acc &acc,
     da = fma(2.0 * p.a2, s.x, p.a1);
     d2a = 2.0 * p.a2;
   } else {
-    double u = (s.x - p.x_min) * p.inv_dx - 0.5;
-    if (!(u >= -3.0)) u = -3.0;  // also catches a NaN position
-    if (u > (double)p.nx + 2.0) u = (double)p.nx + 2.0;
-    const double fi = floor(u + 0.5);
-    const double w = u - fi;
+    double w;
+    const double fi = tsc_cell(p, s.x, w);
     const double tm = 0.5 - w, tp = 0.5 + w;
     const double w0 = 0.5 * (tm * tm), w1 = 0.75 - w * w, w2 = 0.5 * (tp * tp);
     const int idx = (int)fi + 4;
@@ -273,10 +283,38 @@ __device__ __forceinline__ void elem_kick(const KP &p, const Acc &acc,
 
 // Query record and block registration of one element.  A non-finite
 // element or det T <= 0 raises FLAG_NUMERIC and is not registered.
-__device__ __forceinline__ void elem_record(
+//
+// elem_record_box writes the record and returns the element's registration
+// box: the query blocks whose 8x8 sites its validity window's bounding box
+// touches (n = 0 when there is nothing to register).  reg_block tests one
+// block of the box: a block is listed only if the validity window
+// |l| < (dx_m, dv_m), l = A (P - P_m), can hold one of its sites, so sheared
+// windows do not fill the lists of the blocks their bounding box merely
+// touches.  l is linear in P: over the block's 8x8 rectangle of sites (a
+// superset of its live sites at the grid edges) it ranges over l(centre) +-
+// the sum of |A_ij| x half-width.  A block is skipped only when a component
+// stays outside the window by more than a margin covering the rounding of l
+// at the sites, relative to the magnitudes of the products A_ij dP_j (which
+// may cancel), taken at the largest distance of a block site from the
+// element, so that per block only l(centre) remains to compute.
+struct RegBox {
+  int n;              // blocks in the box, wxm per block row
+  int wxm, b0v, ilo, ihi, ga;
+  int opack;          // x offsets (0..7) of the row groups ga, ga + 1, ga + 2
+                      // in bits 0-2, 3-5, 6-8
+  double x, v, axx, axv, avx, avv, limx, limv;
+};
+
+// A box of at most 9 block rows lies in at most three row groups (a group
+// is 8 block rows), whose x offsets the box carries; taller boxes (very
+// sheared elements) compute the offset per block.
+constexpr int REG_NEAR_ROWS = 9;
+
+__device__ __forceinline__ RegBox elem_record_box(
     const KP &p, const ElemState &s, int e, double *__restrict__ rec,
-    double *__restrict__ qm, int *__restrict__ cnt, int *__restrict__ lst,
-    int *__restrict__ flags, int reg) {
+    double *__restrict__ qm, int *__restrict__ flags, int reg) {
+  RegBox B;
+  B.n = 0;
   const double det = fma(s.txx, s.tvv, -(s.txv * s.tvx));
   const bool bad = !(det > 0.0) || !isfinite(det) || !isfinite(s.x) ||
                    !isfinite(s.v);
@@ -311,9 +349,9 @@ __device__ __forceinline__ void elem_record(
                          (1.0 + rel) + 0x1p-20;
   if (bad) {
     atomicOr(flags, FLAG_NUMERIC);
-    return;
+    return B;
   }
-  if (!reg) return;
+  if (!reg) return B;
   const double cx = (s.x - p.x_min) * p.inv_dx - 0.5;
   const double cv = (s.v - p.v_min) * p.inv_dv - 0.5;
   const double vlo = fmax(cv - rvs, -1.0), vhi = fmin(cv + rvs, (double)p.nv);
@@ -325,70 +363,87 @@ __device__ __forceinline__ void elem_record(
     // a row has, is too wide for the nearest-image lists
     if (!(rxs < 0.5 * (double)p.nx - 2.0)) {
       atomicOr(flags, FLAG_WIDE);
-      return;
+      return B;
     }
     ilo = (int)ceil(cx - rxs);
     ihi = (int)floor(cx + rxs);
     if (ihi - ilo > p.nx - 24) {
       atomicOr(flags, FLAG_WIDE);
-      return;
+      return B;
     }
   } else {
     const double xlo = fmax(cx - rxs, -1.0), xhi = fmin(cx + rxs, (double)p.nx);
     ilo = max(0, (int)ceil(xlo));
     ihi = min(p.nx - 1, (int)floor(xhi));
   }
-  if (ilo > ihi || jlo > jhi) return;
+  if (ilo > ihi || jlo > jhi) return B;
   const int b0v = blk(jlo, p.ov, p.obv), b1v = blk(jhi, p.ov, p.obv);
   // blocks per row of the window's box, whatever the row group's x offset
   const int wxm = ((ihi - ilo) >> 3) + 2, wv = b1v - b0v + 1;
   if ((long long)wxm * (long long)wv > SPAN_LIMIT) {
     atomicOr(flags, FLAG_WIDE);
-    return;
+    return B;
   }
-  // slot claims are independent: issue them sixteen at a time and only
-  // then write the ids (one atomic round trip per sixteen blocks).
-  // A block of the box is listed only if the validity window |l| < (dx_m,
-  // dv_m), l = A (P - P_m), can hold one of its sites, so sheared windows
-  // do not fill the lists of the blocks their bounding box merely touches.
-  // l is linear in P: over the block's 8x8 rectangle of sites (a superset
-  // of its live sites at the grid edges) it ranges over l(centre) +- the
-  // sum of |A_ij| x half-width.  A block is skipped only when a component
-  // stays outside the window by more than a margin covering the rounding of
-  // l at the sites, relative to the magnitudes of the products A_ij dP_j
-  // (which may cancel), taken at the largest distance of a block site from
-  // the element, so that per block only l(centre) remains to compute.
   const double hx = 3.5 * p.dx, hv = 3.5 * p.dv;
   const double mxm = (rxs + 8.0) * p.dx, mvm = (rvs + 8.0) * p.dv;
-  const double limx =
+  B.limx =
       p.dxm + 0x1p-36 * (fabs(axx) * (mxm + 1.0) + fabs(axv) * (mvm + 1.0) +
                          p.dxm) + (fabs(axx) * hx + fabs(axv) * hv);
-  const double limv =
+  B.limv =
       p.dvm + 0x1p-36 * (fabs(avx) * (mxm + 1.0) + fabs(avv) * (mvm + 1.0) +
                          p.dvm) + (fabs(avx) * hx + fabs(avv) * hv);
-  const int ga = group_of_brow(p, b0v);
-  const int oa = group_ox(p, ga), ob = group_ox(p, ga + 1);
+  B.ga = group_of_brow(p, b0v);
+  B.opack = group_ox(p, B.ga) | (group_ox(p, B.ga + 1) << 3) |
+            (group_ox(p, B.ga + 2) << 6);
+  B.n = wxm * wv;
+  B.wxm = wxm;
+  B.b0v = b0v;
+  B.ilo = ilo;
+  B.ihi = ihi;
+  B.x = s.x;
+  B.v = s.v;
+  B.axx = axx;
+  B.axv = axv;
+  B.avx = avx;
+  B.avv = avv;
+  return B;
+}
+
+// Block (row qr, column qc) of a registration box: its list index, or -1
+// when the element's validity window cannot reach it.
+template <bool TALL>
+__device__ __forceinline__ int reg_block(const KP &p, const RegBox &B, int qr,
+                                         int qc) {
+  const int bvq = B.b0v + qr;
+  const int gy = group_of_brow(p, bvq);
+  const int o = TALL ? group_ox(p, gy) : (B.opack >> (3 * (gy - B.ga))) & 7;
+  const int bxq = blk(B.ilo, o, 1) + qc;
+  const int i0 = o + 8 * (bxq - 1), j0 = p.ov + 8 * (bvq - p.obv);
+  const double cx = (p.x_min + (double)(i0 + 4) * p.dx) - B.x;
+  const double cv = (p.v_min + (double)(j0 + 4) * p.dv) - B.v;
+  const double lxc = B.axx * cx + B.axv * cv, lvc = B.avx * cx + B.avv * cv;
+  if (bxq <= blk(B.ihi, o, 1) && fabs(lxc) < B.limx && fabs(lvc) < B.limv)
+    return bvq * p.nbx + (p.per ? ((bxq % p.nbl) + p.nbl) % p.nbl : bxq);
+  return -1;
+}
+
+// Register blocks q0 .. nblk - 1 of a box with one global slot claim each:
+// the claims are independent, so they are issued sixteen at a time and
+// only then are the ids written (one atomic round trip per sixteen blocks).
+template <bool TALL>
+__device__ __forceinline__ void reg_claims(const KP &p, const RegBox &B,
+                                           int q0, int e, int *__restrict__ cnt,
+                                           int *__restrict__ lst) {
   constexpr int RB = 16;
-  const int nblk = wxm * wv;
-  int qr = 0, qc = 0;  // block row and column of q = q0 + k in the box
-  for (int q0 = 0; q0 < nblk; q0 += RB) {
+  int qr = q0 / B.wxm, qc = q0 % B.wxm;
+  for (int qb = q0; qb < B.n; qb += RB) {
     int bb[RB], slot[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
       bb[k] = -1;
-      if (q0 + k < nblk) {
-        const int bvq = b0v + qr;
-        const int gy = group_of_brow(p, bvq);
-        const int o = gy == ga ? oa : (gy == ga + 1 ? ob : group_ox(p, gy));
-        const int bxq = blk(ilo, o, 1) + qc;
-        const int i0 = o + 8 * (bxq - 1), j0 = p.ov + 8 * (bvq - p.obv);
-        const double cx = (p.x_min + (double)(i0 + 4) * p.dx) - s.x;
-        const double cv = (p.v_min + (double)(j0 + 4) * p.dv) - s.v;
-        const double lxc = axx * cx + axv * cv, lvc = avx * cx + avv * cv;
-        if (bxq <= blk(ihi, o, 1) && fabs(lxc) < limx && fabs(lvc) < limv)
-          bb[k] = bvq * p.nbx +
-                  (p.per ? ((bxq % p.nbl) + p.nbl) % p.nbl : bxq);
-        if (++qc == wxm) {
+      if (qb + k < B.n) {
+        bb[k] = reg_block<TALL>(p, B, qr, qc);
+        if (++qc == B.wxm) {
           qc = 0;
           ++qr;
         }
@@ -401,6 +456,23 @@ __device__ __forceinline__ void elem_record(
     for (int k = 0; k < RB; ++k)
       if (slot[k] < p.cap) lst[(size_t)bb[k] * p.cap + slot[k]] = e;
   }
+}
+
+__device__ __forceinline__ void reg_direct(const KP &p, const RegBox &B,
+                                           int q0, int e, int *__restrict__ cnt,
+                                           int *__restrict__ lst) {
+  if (B.n / B.wxm > REG_NEAR_ROWS)
+    reg_claims<true>(p, B, q0, e, cnt, lst);
+  else
+    reg_claims<false>(p, B, q0, e, cnt, lst);
+}
+
+__device__ __forceinline__ void elem_record(
+    const KP &p, const ElemState &s, int e, double *__restrict__ rec,
+    double *__restrict__ qm, int *__restrict__ cnt, int *__restrict__ lst,
+    int *__restrict__ flags, int reg) {
+  const RegBox B = elem_record_box(p, s, e, rec, qm, flags, reg);
+  if (B.n > 0) reg_direct(p, B, 0, e, cnt, lst);
 }
 
 __global__ __launch_bounds__(256) void k_elem(
@@ -898,6 +970,44 @@ struct AccFromMass {
   }
 };
 
+// The same force for one element without the whole M_left table (isolated
+// x): the six cumulative masses M_left(i0 - 3 .. i0 + 2) that the dual TSC
+// around site i0 needs, each the carry of its 64-site chunk plus the
+// chunk's published prefix, give a at i0 - 2 .. i0 + 2 and then a, a', a''
+// at i0 - 1 .. i0 + 1 with the operations of acc_site and acc_from_mass
+// (the same values bit for bit).
+struct AccWindow {
+  const KP &p;
+  double a[5];  // a at sites i0 - 2 .. i0 + 2
+  int q0;       // table index i0 + 4 of site i0
+  __device__ __forceinline__ AccWindow(const KP &p_, int i0,
+                                       const double *car,
+                                       const double *__restrict__ Mc,
+                                       double Mtot)
+      : p(p_), q0(i0 + 4) {
+    double m[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const int j = i0 - 3 + d;
+      m[d] = (j < 0) ? 0.0
+             : (j >= p.nx) ? Mtot
+                           : car[j / MCHUNK] + ld_coherent(Mc + j);
+    }
+#pragma unroll
+    for (int d = 0; d < 5; ++d) a[d] = p.G * ((Mtot - m[d + 1]) - m[d]);
+  }
+  __device__ __forceinline__ void at(int q, double &a0, double &da,
+                                     double &d2a) const {
+    const int k = q - q0;  // -1, 0 or 1
+    const double am = (k < 0) ? a[0] : (k == 0) ? a[1] : a[2];
+    a0 = (k < 0) ? a[1] : (k == 0) ? a[2] : a[3];
+    const double ap = (k < 0) ? a[2] : (k == 0) ? a[3] : a[4];
+    const double two_dx = 2.0 * p.dx, dx2 = p.dx * p.dx;
+    da = (ap - am) / two_dx;
+    d2a = ((ap + am) - 2.0 * a0) / dx2;
+  }
+};
+
 // Largest value over the 64 lanes of a wavefront (order-free: max is exact).
 __device__ __forceinline__ double wave_max(double m) {
 #pragma unroll
@@ -1281,14 +1391,26 @@ __global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
 // nch workgroups each sum one 64-column chunk (column sums in increasing
 // group order, the chunk's sequential prefix and total) and publish it;
 // after a grid-wide wait every workgroup adds the carries sequentially and
-// rebuilds M_left in LDS from the published chunks.  The producers are the
-// lowest-numbered workgroups and wait on nothing, so in-order dispatch runs
-// them first; the grid is launched only when it fits on the device at
+// takes M_left from the published chunks (the whole table with periodic x,
+// else the six values around each element's TSC cell).  The producers are
+// the lowest-numbered workgroups and wait on nothing, so in-order dispatch
+// runs them first; the grid is launched only when it fits on the device at
 // once, and the wait is bounded (FLAG_SYNC instead of a hang).  fsync
 // counts published chunks over the run's lifetime; this launch waits for
 // target.
 constexpr int SYNC_SPIN_LIMIT = 1 << 20;  // about a second
 constexpr int ELEMC_WG = 256;
+// Elements of the shared-field pass come in PATCH x PATCH lattice patches,
+// one per workgroup: the block lists an element registers into are mostly
+// those of its neighbours in the same workgroup, which keeps the slot
+// claims of a workgroup on few cache lines of the counts.
+constexpr int PATCH = 16;
+static_assert(PATCH * PATCH == ELEMC_WG, "one element per thread");
+
+// Number of element patches of a run.
+__host__ __device__ __forceinline__ int elem_patches(int mx, int mv) {
+  return ((mx + PATCH - 1) / PATCH) * ((mv + PATCH - 1) / PATCH);
+}
 
 __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
     KP p, const double *__restrict__ part, double *__restrict__ Mc,
@@ -1301,16 +1423,21 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
   __shared__ double M[FIELD1_MAX];
   __shared__ double car[FIELD1_MAX / MCHUNK + 1];
   __shared__ int s_ok;
-  __shared__ double s_rmax;
+  __shared__ double s_rmax, s_mtot;
   const int tid = threadIdx.x, nx = p.nx;
   const int nch = (nx + MCHUNK - 1) / MCHUNK;
   const long long gid = (long long)blockIdx.x * blockDim.x + tid;
   const long long gsz = (long long)gridDim.x * blockDim.x;
-  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
-  const int e = (int)gid;
+  // this thread's element: (k, l) in patch blockIdx.x
+  const int npx = (p.mx + PATCH - 1) / PATCH;
+  const int pat = blockIdx.x;
+  const int ek = (pat % npx) * PATCH + tid % PATCH;
+  const int el = (pat / npx) * PATCH + tid / PATCH;
+  const bool has = pat < elem_patches(p.mx, p.mv) && ek < p.mx && el < p.mv;
+  const int e = has ? el * p.mx + ek : 0;
   const size_t E = (size_t)p.E;
   ElemState s;
-  if (e < p.E) elem_load(st, E, e, s);  // in flight during the field
+  if (has) elem_load(st, E, e, s);  // in flight during the field
   const int c = blockIdx.x;
   if (c < nch && tid < 64) {
     // chunk c: one lane per column
@@ -1319,13 +1446,15 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
     if (tid < n) {
       const int i = i0 + tid;
       double x = 0.0;
-      for (int g0 = 0; g0 < p.ngy; g0 += 16) {
-        double v[16];
+      // every row group's partial requested at once (one memory round trip
+      // for grids up to 40 groups), then added in increasing group order
+      for (int g0 = 0; g0 < p.ngy; g0 += 40) {
+        double v[40];
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
+        for (int u = 0; u < 40; ++u)
           v[u] = (g0 + u < p.ngy) ? part[(size_t)(g0 + u) * nx + i] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
+        for (int u = 0; u < 40; ++u)
           if (g0 + u < p.ngy) x += v[u];
       }
       const double rho = p.dv * x;
@@ -1365,38 +1494,68 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
     s_ok = ok;
   }
   __syncthreads();
-  // carries and M_left from the published chunks
-  for (int k = tid; k < nch; k += ELEMC_WG) car[k] = ld_coherent(ctot + k);
-  for (int i = tid; i < nx; i += ELEMC_WG) M[i] = ld_coherent(Mc + i);
+  // the previous lists' counts are cleared only now: stores made before the
+  // producers' release would be written back with it
+  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
+  // carries from the published chunk totals (one lane per chunk, the
+  // sequential sum across the lanes); with periodic x the whole M_left
+  // table (the mean of B needs every site), else each element reads the six
+  // chunk prefixes around its TSC cell (AccWindow)
+  if (p.per)
+    for (int i = tid; i < nx; i += ELEMC_WG) M[i] = ld_coherent(Mc + i);
+  if (tid < 64) {
+    // one lane per chunk: totals, the last prefix and the chunk maxima in
+    // one round trip
+    if (tid < nch) car[tid] = ld_coherent(ctot + tid);
+    if (tid == 0) s_mtot = ld_coherent(Mc + nx - 1);
+    double m = (p.clk && tid < nch) ? ld_coherent(cmax + tid) : 0.0;
+    if (p.clk) {
+      m = wave_max(m);
+      if (tid == 0) s_rmax = m;
+    }
+  }
   __syncthreads();
   if (tid == 0) {
+    // exclusive carries, sequential in chunk order
     double carry = 0.0;
     for (int k = 0; k < nch; ++k) {
       const double t = car[k];
       car[k] = carry;
       carry = carry + t;
     }
-    if (p.clk) {
-      double m = 0.0;
-      for (int k = 0; k < nch; ++k) m = fmax(m, ld_coherent(cmax + k));
-      s_rmax = m;
-    }
+    s_mtot = car[nch - 1] + s_mtot;
   }
   __syncthreads();
-  for (int i = tid; i < nx; i += ELEMC_WG) M[i] = car[i / MCHUNK] + M[i];
-  __syncthreads();
-  const double Mtot = M[nx - 1];
-  const double Bbar = p.per ? periodic_mean<ELEMC_WG>(p, M, Mtot, car) : 0.0;
+  double Mtot, Bbar = 0.0;
+  if (p.per) {
+    for (int i = tid; i < nx; i += ELEMC_WG) M[i] = car[i / MCHUNK] + M[i];
+    __syncthreads();
+    Mtot = M[nx - 1];
+    Bbar = periodic_mean<ELEMC_WG>(p, M, Mtot, car);
+  } else {
+    Mtot = s_mtot;
+  }
   if (!s_ok) return;
   const double dtn = elem_clock(p, p.clk ? s_rmax : 0.0, predict, gid == 0);
-  if (e >= p.E) return;
-  elem_kick(p, AccFromMass{p, M, Mtot, Bbar}, s);
-  if (predict) {
-    p.h = 0.5 * dtn;
-    elem_drift(p, s);
+  if (has) {
+    if (p.per || p.force_mode != 0) {
+      elem_kick(p, AccFromMass{p, M, Mtot, Bbar}, s);
+    } else {
+      double w;
+      const int i0 = (int)tsc_cell(p, s.x, w);
+      elem_kick(p, AccWindow(p, i0, car, Mc, Mtot), s);
+    }
+    if (predict) {
+      p.h = 0.5 * dtn;
+      elem_drift(p, s);
+    }
+    elem_store(st, E, e, s);
   }
-  elem_store(st, E, e, s);
-  if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
+  if (!predict) return;
+  RegBox B;
+  B.n = 0;
+  if (has) B = elem_record_box(p, s, e, rec, qm, flags, reg);
+  if (B.n > 0) reg_direct(p, B, 0, e, cnt_reg, lst);
 }
 
 // ------------------------------------------------------- reconstruction
