@@ -192,7 +192,7 @@ __global__ __launch_bounds__(FIT_THREADS) void kb_fit_x(
     const PhaseItem pi = tab->it[q];
     const RunDesc<FT> &R = runs[pi.slot];
     const KP &p = R.k;
-    fit_x_rows<FT>(p, R.F, R.T, R.tab, R.tab + p.nx, item - pi.begin, S);
+    fit_x_rows<FT>(p, R.F, R.T, R.tab, item - pi.begin, S);
   }
 }
 
@@ -206,8 +206,7 @@ __global__ __launch_bounds__(FIT_THREADS) void kb_fit_v(
     const PhaseItem pi = tab->it[q];
     const RunDesc<FT> &R = runs[pi.slot];
     const KP &p = R.k;
-    fit_v_cols<FT>(p, R.T, R.C, R.tab + 2 * p.nx, R.tab + 2 * p.nx + p.nv,
-                   item - pi.begin, S);
+    fit_v_cols<FT>(p, R.T, R.C, R.tab, item - pi.begin, S);
   }
 }
 

@@ -160,8 +160,9 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.acc = take((size_t)3 * (k.nx + 8) * 8);
   L.dpart = take((size_t)DPS * k.nbx * k.ngy * 8);
   L.dout = take(16 * 8);
-  // spline tables: x pivots, v pivots, and (periodic x) z and den
-  L.tab = take((size_t)(3 * k.nx + 2 * k.nv + 1) * fb);
+  // spline tables: x pivots, v pivots, (periodic x) z and den, and the
+  // pivots of a system starting at an artificial first row
+  L.tab = take((size_t)(3 * k.nx + 2 * k.nv + 1 + FIT_TW_MAX) * fb);
   L.total = o;
   return L;
 }
@@ -437,23 +438,21 @@ int fit_spline_t(vp_ctx *c, hipStream_t st) {
   const KP &k = c->k;
   ProfScope ps(c, PK_FIT, st);
   FT *tab = c->at<FT>(c->L.tab);
-  FT *cpx = tab, *rix = tab + k.nx, *cpv = tab + 2 * k.nx,
-     *riv = tab + 2 * k.nx + k.nv, *zx = tab + 2 * k.nx + 2 * k.nv,
-     *den = tab + 3 * k.nx + 2 * k.nv;
-  hipLaunchKernelGGL((k_fit_x<FT>), dim3(grid_for(k.nv, FIT_LINES)),
+  FT *zx = tab + 2 * k.nx + 2 * k.nv, *den = tab + 3 * k.nx + 2 * k.nv;
+  hipLaunchKernelGGL((k_fit_x<FT>),
+                     dim3(grid_for(k.nv, FIT_LINES) * fit_segments<FT>(k.nx)),
                      dim3(FIT_THREADS), 0,
-                     st, k, c->at<FT>(c->L.F), c->at<FT>(c->L.T), cpx,
-                     rix);
+                     st, k, c->at<FT>(c->L.F), c->at<FT>(c->L.T), tab);
   VP_LAUNCH_CHECK(c, "k_fit_x");
   if (k.per) {
     hipLaunchKernelGGL((k_fit_x_cyclic<FT>), dim3(k.nv), dim3(256), 0,
                        st, k, c->at<FT>(c->L.T), zx, den);
     VP_LAUNCH_CHECK(c, "k_fit_x_cyclic");
   }
-  hipLaunchKernelGGL((k_fit_v<FT>), dim3(grid_for(k.nx, FIT_LINES)),
+  hipLaunchKernelGGL((k_fit_v<FT>),
+                     dim3(grid_for(k.nx, FIT_LINES) * fit_segments<FT>(k.nv)),
                      dim3(FIT_THREADS), 0,
-                     st, k, c->at<FT>(c->L.T), c->at<FT>(c->L.C), cpv,
-                     riv);
+                     st, k, c->at<FT>(c->L.T), c->at<FT>(c->L.C), tab);
   VP_LAUNCH_CHECK(c, "k_fit_v");
   if (k.per) {
     hipLaunchKernelGGL((k_ghost_periodic<FT>), dim3(grid_for(k.nv + 2, 256)),
@@ -733,6 +732,15 @@ int upload_tables(vp_ctx *c) {
   all.insert(all.end(), riv.begin(), riv.end());
   all.insert(all.end(), zx.begin(), zx.end());
   all.push_back(den);
+  // 1/den of the (1, 4, 1) system from an artificial first row (4, 1): the
+  // forward pivots of the first tile of a fit segment that does not start
+  // at the line's start
+  FT cp = (FT)0;
+  for (int q = 0; q < FIT_TW_MAX; ++q) {
+    const FT r = (FT)1 / ((FT)4 - cp);
+    all.push_back(r);
+    cp = r;
+  }
   // the host copy lives as long as the context, so no wait is needed
   c->host_tab.assign(reinterpret_cast<const char *>(all.data()),
                      reinterpret_cast<const char *>(all.data() + all.size()));
@@ -1436,8 +1444,12 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
       const int hr = 2 * (step_after - (int)c->reset_step);
       add(PH_RM_PRED, q, el_items, EA_PRED | EA_REG | regr, hr);
       add(PH_RM_EVAL, q, tiles, cr, hr);
-      add(PH_FIT_X, q, ceil_div(k.nv, 64), 0);
-      add(PH_FIT_V, q, ceil_div(k.nx, 64), 0);
+      const int sx = c->mixed() ? fit_segments<float>(k.nx)
+                                : fit_segments<double>(k.nx);
+      const int sv = c->mixed() ? fit_segments<float>(k.nv)
+                                : fit_segments<double>(k.nv);
+      add(PH_FIT_X, q, ceil_div(k.nv, 64) * sx, 0);
+      add(PH_FIT_V, q, ceil_div(k.nx, 64) * sv, 0);
       add(PH_GHOST, q, ceil_div(k.nv + 2, 256), 0);
       add(PH_RESET, q, elz_items, EA_RESET | EA_ZERO | zr);
       c->reset_step = step_after;

@@ -1953,10 +1953,26 @@ __global__ __launch_bounds__(1024) void k_diag(
 // and a ring of three LDS tiles with coalesced accesses (the next tile is
 // loaded while the current one is solved, the previous one is written
 // back).  Forward sweep, then back substitution over the tiles in reverse.
+//
+// Long lines are solved in segments, so that a line's recurrences run in
+// parallel instead of one after another: a segment of FIT_SEG_TILES tiles
+// is solved over its positions extended by one tile on each side, as the
+// system truncated there (its first row without the sub-diagonal, its last
+// without the super-diagonal).  The inverse of the (1, 4, 1) matrix decays
+// like (2 - sqrt 3)^d = 0.268^d with the distance d from a row, so the
+// truncation changes the segment's own values by 0.268^TW of the solution
+// (5e-19 for the 32-position double tiles, 3e-37 for the 64-position float
+// ones): the same solution to rounding.  The forward sweep keeps the
+// segment's eliminated values and sums the back substitution over the last
+// tile, c_b = sum_k (-1)^k (prod_{j<k} cp_{b+j}) d_{b+k}, which starts the
+// back substitution of the segment at its end b.  A line of at most one
+// segment is the plain Thomas elimination.
 constexpr int FIT_LINES = 64;
 constexpr int FIT_MOVERS = 256;                 // wavefronts 1-4
 constexpr int FIT_THREADS = 64 + FIT_MOVERS;
 constexpr int FIT_NB = 3;
+constexpr int FIT_SEG_TILES = 8;
+constexpr int FIT_TW_MAX = 64;  // tile width of the float fit
 
 template <typename FT>
 struct FitLds {
@@ -1969,6 +1985,15 @@ struct FitLds {
 };
 static_assert(FitLds<float>::NV * 4 * FIT_MOVERS == FIT_LINES * 64, "tile");
 static_assert(FitLds<double>::NV * 2 * FIT_MOVERS == FIT_LINES * 32, "tile");
+static_assert(FitLds<float>::TW == FIT_TW_MAX, "artificial pivot table");
+
+// Segments of a line of n positions (each FIT_SEG_TILES tiles, the last
+// one shorter).
+template <typename FT>
+__host__ __device__ __forceinline__ int fit_segments(int n) {
+  constexpr int m = FIT_SEG_TILES * FitLds<FT>::TW;
+  return (n + m - 1) / m;
+}
 
 // Geometry of one pass: element (line l, position i) lives at
 // base[l * ls + i * ps]; LINE_CONTIG says ls == 1 (columns), else ps == 1.
@@ -1980,9 +2005,12 @@ struct FitLine {
   FT *out;
   long in_ls, in_ps, out_ls, out_ps;
   const FT *coef;  // 1/den (forward) or cp (backward), per position
+  const FT *coef_art;  // forward 1/den of a system starting at pb > 0
   int n;           // positions
   int nl;          // lines of this workgroup (<= 64)
   int last2;       // the last row's sub-diagonal is 2 (mirror end), else 1
+  int pb, pe;      // forward: the positions [pb, pe) eliminated
+  int sa, sb;      // the segment [sa, sb): stored, back-substituted
 };
 
 template <typename FT>
@@ -2046,7 +2074,8 @@ __device__ __forceinline__ void fit_load(const FitLine<FT> &G, int i0,
 #pragma unroll
       for (int u = 0; u < FitLds<FT>::VEC; ++u) r.x[q].v[u] = (FT)0;
   }
-  r.c = (mt < TW && i0 + mt < G.n) ? G.coef[i0 + mt] : (FT)0;
+  const FT *cf = (i0 == G.pb && G.pb > 0) ? G.coef_art - i0 : G.coef;
+  r.c = (mt < TW && i0 + mt < G.n) ? cf[i0 + mt] : (FT)0;
 }
 
 template <typename FT, bool LINE_CONTIG>
@@ -2089,22 +2118,29 @@ __device__ __forceinline__ void fit_store(const FitLine<FT> &G, int i0,
   }
 }
 
-// One sweep over all tiles.  BACK = false: forward elimination
-// d_i = (6 f_i - s_i d_{i-1}) / den_i with s_i = 2 at the last position,
-// else 1 (d_{-1} = 0 gives the first row exactly).  BACK = true: back
-// substitution c_i = d_i - cp_i c_{i+1} from the last position (c_n = 0
-// gives c_{n-1} = d_{n-1} exactly).  GHOST: also write the mirror rows
-// c(-1) = c(1) and c(n) = c(n - 2) of every line.
+// One sweep over the tiles of a segment.  BACK = false: forward
+// elimination over [pb, pe), d_i = (6 f_i - s_i d_{i-1}) / den_i with s_i =
+// 2 at the line's last position, else 1 (d_{pb-1} = 0 gives the first row
+// of the line, or of the truncated system, exactly); the segment's values
+// are stored and, over the tile after it, the back substitution's value at
+// sb is summed and returned.  BACK = true: back substitution c_i = d_i -
+// cp_i c_{i+1} over the segment from c_sb = acc0 (c_n = 0 gives c_{n-1} =
+// d_{n-1} exactly).  GHOST: also write the mirror rows c(-1) = c(1) and
+// c(n) = c(n - 2) of every line.  Tiles are TW positions from a multiple
+// of TW (pb, sa and the segment ends are multiples of TW, or n).
 template <typename FT, bool LINE_CONTIG, bool BACK, bool GHOST>
-__device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
-                                          FitLds<FT> &S) {
+__device__ __forceinline__ FT fit_sweep(const FitLine<FT> &G, FitLds<FT> &S,
+                                        FT acc0 = (FT)0) {
   constexpr int TW = FitLds<FT>::TW, LP = FitLds<FT>::LP;
   const int n = G.n;
-  const int nt = (n + TW - 1) / TW;
+  const int p0 = BACK ? G.sa : G.pb, p1 = BACK ? G.sb : G.pe;
+  const int nt = (p1 - p0 + TW - 1) / TW;
+  const int tlast = p0 + (nt - 1) * TW;
   const bool mover = threadIdx.x >= 64;
   const int lane = threadIdx.x & 63;
   // tile t of the sweep order starts at position tile_i0(t)
-  auto tile_i0 = [&](int t) { return (BACK ? nt - 1 - t : t) * TW; };
+  auto tile_i0 = [&](int t) { return BACK ? tlast - t * TW : p0 + t * TW; };
+  auto stored = [&](int i0) { return i0 >= G.sa && i0 < G.sb; };
   // two register sets: tile u is loaded into set u % 2 three iterations
   // before it is needed and put into LDS one iteration before
   FitRegs<FT> ra, rb;
@@ -2122,7 +2158,7 @@ __device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
       if (t + 3 < nt) fit_load<FT, LINE_CONTIG>(G, tile_i0(t + 3), rs);
     }
   };
-  FT acc = (FT)0;
+  FT acc = acc0, csum = (FT)0, w = (FT)1;
   for (int t = 0; t < nt; ++t) {
     const int b = t % FIT_NB;
     if (!mover) {
@@ -2133,7 +2169,16 @@ __device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
       // positions [0, kb) in unguarded blocks of 16; the tile's remainder
       // (and the last position of the line, whose sub-diagonal is 2) alone
       const int kb = (i0 + kn == n) ? ((kn - 1) & ~15) : kn;
-      if (!BACK) {
+      if (!BACK && i0 >= G.sb) {
+        // the tile after the segment: eliminate, and sum the back
+        // substitution from its end down to sb
+        for (int k = 0; k < kn; ++k) {
+          const FT sd = (G.last2 && i0 + k == n - 1) ? (FT)2 * acc : acc;
+          acc = ((FT)6 * col[k * LP] - sd) * cf[k];
+          csum = fma(w, acc, csum);
+          w = -w * cf[k];
+        }
+      } else if (!BACK) {
         for (int k0 = 0; k0 < kb; k0 += 16) {
           FT v[16], c[16];
 #pragma unroll
@@ -2193,7 +2238,7 @@ __device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
         }
       }
     } else {
-      if (t >= 1)
+      if (t >= 1 && stored(tile_i0(t - 1)))
         fit_store<FT, LINE_CONTIG>(G, tile_i0(t - 1), S.buf[(t - 1) % FIT_NB]);
       if (t & 1)
         mover_step(t, ra);
@@ -2202,18 +2247,45 @@ __device__ __forceinline__ void fit_sweep(const FitLine<FT> &G,
     }
     __syncthreads();
   }
-  if (mover)
+  if (mover && stored(tile_i0(nt - 1)))
     fit_store<FT, LINE_CONTIG>(G, tile_i0(nt - 1), S.buf[(nt - 1) % FIT_NB]);
   __syncthreads();
+  return csum;
 }
 
-// Solve along x for rows [64 chunk, 64 chunk + 64): F (padded) -> T.
+// Segment seg of a line of n positions: the stored range [sa, sb) and the
+// eliminated range [pb, pe), extended by one tile where the segment does not
+// reach the line's end.
+template <typename FT>
+__device__ __forceinline__ void fit_segment(FitLine<FT> &G, int seg) {
+  constexpr int TW = FitLds<FT>::TW, m = FIT_SEG_TILES * TW;
+  G.sa = seg * m;
+  G.sb = min(G.n, G.sa + m);
+  G.pb = (G.sa > 0) ? G.sa - TW : 0;
+  G.pe = min(G.n, G.sb + TW);
+}
+
+// Spline tables (one array, see upload_tables): x pivots cp and 1/den,
+// v pivots cp and 1/den, the periodic z and den, and 1/den of a system that
+// starts at an artificial first row.
+template <typename FT>
+struct FitTables {
+  const FT *cpx, *rix, *cpv, *riv, *art;
+  __device__ __forceinline__ FitTables(const KP &p, const FT *tab)
+      : cpx(tab), rix(tab + p.nx), cpv(tab + 2 * p.nx),
+        riv(tab + 2 * p.nx + p.nv), art(tab + 3 * p.nx + 2 * p.nv + 1) {}
+};
+
+// Solve along x, work item w: rows [64 chunk, 64 chunk + 64) of segment seg
+// (w = chunk * segments + seg): F (padded) -> T.
 template <typename FT>
 __device__ __forceinline__ void fit_x_rows(const KP &p, const FT *__restrict__ F,
                                           FT *__restrict__ T,
-                                          const FT *__restrict__ cpx,
-                                          const FT *__restrict__ rix,
-                                          const int chunk, FitLds<FT> &S) {
+                                          const FT *__restrict__ tab,
+                                          const int w, FitLds<FT> &S) {
+  const FitTables<FT> tb(p, tab);
+  const int nseg = fit_segments<FT>(p.nx);
+  const int chunk = w / nseg, seg = w - chunk * nseg;
   const int j0 = chunk * FIT_LINES;
   FitLine<FT> G;
   G.n = p.nx;
@@ -2224,23 +2296,27 @@ __device__ __forceinline__ void fit_x_rows(const KP &p, const FT *__restrict__ F
   G.out = T + (size_t)j0 * p.nx;
   G.out_ls = p.nx;
   G.out_ps = 1;
-  G.coef = rix;
+  G.coef = tb.rix;
+  G.coef_art = tb.art;
   G.last2 = !p.per;  // periodic x: the cyclic system's tridiagonal part
-  fit_sweep<FT, false, false, false>(G, S);
+  fit_segment<FT>(G, seg);
+  const FT cb = fit_sweep<FT, false, false, false>(G, S);
   G.in = G.out;
   G.in_ls = G.out_ls;
-  G.coef = cpx;
-  fit_sweep<FT, false, true, false>(G, S);
+  G.coef = tb.cpx;
+  fit_sweep<FT, false, true, false>(G, S, cb);
 }
 
-// Solve along v for columns [64 chunk, 64 chunk + 64): T -> C (padded, with
-// the mirror ghost rows).
+// Solve along v, work item w: columns [64 chunk, 64 chunk + 64) of segment
+// seg: T -> C (padded, with the mirror ghost rows).
 template <typename FT>
 __device__ __forceinline__ void fit_v_cols(const KP &p, const FT *__restrict__ T,
                                           FT *__restrict__ C,
-                                          const FT *__restrict__ cpv,
-                                          const FT *__restrict__ riv,
-                                          const int chunk, FitLds<FT> &S) {
+                                          const FT *__restrict__ tab,
+                                          const int w, FitLds<FT> &S) {
+  const FitTables<FT> tb(p, tab);
+  const int nseg = fit_segments<FT>(p.nv);
+  const int chunk = w / nseg, seg = w - chunk * nseg;
   const int i0 = chunk * FIT_LINES;
   FitLine<FT> G;
   G.n = p.nv;
@@ -2251,29 +2327,31 @@ __device__ __forceinline__ void fit_v_cols(const KP &p, const FT *__restrict__ T
   G.out = C + (long)PV * p.pitch + PX + i0;
   G.out_ls = 1;
   G.out_ps = p.pitch;
-  G.coef = riv;
+  G.coef = tb.riv;
+  G.coef_art = tb.art;
   G.last2 = 1;
-  fit_sweep<FT, true, false, false>(G, S);
+  fit_segment<FT>(G, seg);
+  const FT cb = fit_sweep<FT, true, false, false>(G, S);
   G.in = G.out;
   G.in_ps = G.out_ps;
-  G.coef = cpv;
-  fit_sweep<FT, true, true, true>(G, S);
+  G.coef = tb.cpv;
+  fit_sweep<FT, true, true, true>(G, S, cb);
 }
 
 template <typename FT>
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_x(
     KP p, const FT *__restrict__ F, FT *__restrict__ T,
-    const FT *__restrict__ cpx, const FT *__restrict__ rix) {
+    const FT *__restrict__ tab) {
   __shared__ FitLds<FT> S;
-  fit_x_rows<FT>(p, F, T, cpx, rix, blockIdx.x, S);
+  fit_x_rows<FT>(p, F, T, tab, blockIdx.x, S);
 }
 
 template <typename FT>
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_v(
     KP p, const FT *__restrict__ T, FT *__restrict__ C,
-    const FT *__restrict__ cpv, const FT *__restrict__ riv) {
+    const FT *__restrict__ tab) {
   __shared__ FitLds<FT> S;
-  fit_v_cols<FT>(p, T, C, cpv, riv, blockIdx.x, S);
+  fit_v_cols<FT>(p, T, C, tab, blockIdx.x, S);
 }
 
 // Mirror ghost columns c(-1, j) = c(1, j), c(nx, j) = c(nx - 2, j) for
