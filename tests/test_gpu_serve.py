@@ -125,3 +125,49 @@ def test_rejects_wrong_precision(vp):
     res, st = srv.run(reqs)
     assert res[0]["status"] == vp.EINVAL and st["completed"] == 1
     srv.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_large_requests_equal_standalone(vp, orc, precision):
+    """The upper end of the serving mix: 1024^2 and 2048^2 grids with
+    element strides 4 and 8, run together through two resamplings each.
+    Every request is bit for bit its standalone run (the batched kernels at
+    these sizes); in FP64 one request also matches the oracle on a seeded
+    sample of sites."""
+    import torch
+    rng = np.random.default_rng(95)
+    box = (-1.0, 1.0, -1.0, 1.0)
+    fdt = torch.float32 if precision == "mixed" else torch.float64
+    reqs = []
+    for i, (n, s) in enumerate([(1024, 4), (1024, 8), (2048, 4), (2048, 8)]):
+        f0 = W.finish(W.halo_sum(n, n, box, rng, 3), box, 1.0)
+        reqs.append(dict(
+            params=dict(nx=n, sx=s, dt=5e-4, n_s=25, precision=precision),
+            f0=torch.as_tensor(f0, device="cuda:0"),
+            out=torch.full((n, n), float("nan"), dtype=fdt, device="cuda:0"),
+            nsteps=60, tag=200 + i, arrival_s=0.002 * i))
+    print(f"[serve large] {precision}", flush=True)
+    srv = vp.Server(precision=precision, max_active=4, pool_bytes=1 << 30)
+    res, st = srv.run(reqs)
+    torch.cuda.synchronize()
+    assert st["completed"] == len(reqs) and st["max_active"] >= 2
+    for r, x in zip(reqs, res):
+        assert x["status"] == 0
+        got = r["out"].cpu().numpy()
+        assert np.isfinite(got).all()
+        assert np.array_equal(got, standalone(vp, r)), r["tag"]
+    srv.close()
+    if precision != "fp64":
+        return
+    r = reqs[1]
+    n = r["params"]["nx"]
+    p = dict(r["params"])
+    p.pop("precision")
+    o = orc.Oracle(**p)
+    o.init_conditions(r["f0"].cpu().numpy())
+    o.step(r["nsteps"])
+    srng = np.random.default_rng(7)
+    j, i = srng.integers(0, n, 4096), srng.integers(0, n, 4096)
+    ref = o.reconstruct_sites(j.astype(np.int64) * n + i)
+    got = r["out"].cpu().numpy()[j, i]
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
