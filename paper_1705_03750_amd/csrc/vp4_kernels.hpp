@@ -662,8 +662,18 @@ __global__ __launch_bounds__(256) void k4_recon(
 // axis when an axis needs three; x, y wrap with a one-period shift), W(2d)
 // blend of their Q, tensor spline of F_ini at Q_r; u, w edge rows zero.
 // Writes into out (F_ini when resampling).
+//
+// Four wavefronts per SIMD (at most 128 VGPRs): the per-lane gathers of the
+// neighbours' records need the latency hiding.  The slot offsets and the
+// lattice wrap are selects, not branches that store into small arrays: the
+// branch form, once the register budget made the compiler keep the offsets
+// as one 4-lane vector, was miscompiled at this budget (the control-flow
+// structurizer rebuilt that vector's phi with an undefined incoming value on
+// the path q > 7 of the third axis, so slot 8 re-used slot 7's offsets, the
+// diagonal (0, 0, +1, +1) with zero weight, and the +1 neighbour along the
+// fourth axis dropped out of the blend).
 template <typename FT>
-__global__ __launch_bounds__(256) void k4_remap(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k4_remap(
     KP p, const double *__restrict__ rec, const int *__restrict__ cnt,
     const int *__restrict__ lst, const int *__restrict__ flags,
     const FT *__restrict__ C, FT *__restrict__ out) {
@@ -702,6 +712,7 @@ __global__ __launch_bounds__(256) void k4_remap(
   // -1 on axes 3, 2, 1, 0, the centre, +1 on axes 0, 1, 2, 3, those outside
   // [lo, hi] skipped.
   double sw = 0.0, sq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
   for (int q = 0; q < 16; ++q) {
     int d[4];
     bool use = !three || q == 4;
@@ -719,31 +730,27 @@ __global__ __launch_bounds__(256) void k4_remap(
         d[a] = 0;
       }
     }
-    if (!use) continue;
     int kk[4];
-    double shift[4] = {0.0, 0.0, 0.0, 0.0};
-    bool ok = true;
+    double shift[2];
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
-      int k = k0[a] + d[a];
-      const int nl = a < 2 ? p.ms : p.mv;
-      if (k < 0 || k >= nl) {
-        if (a >= 2) {
-          ok = false;
-          break;
-        }
-        shift[a] = (k < 0) ? -p.L : p.L;
-        k = (k < 0) ? k + nl : k - nl;
+      const int k = k0[a] + d[a];
+      if (a < 2) {  // x, y wrap with a one-period shift
+        shift[a] = k < 0 ? -p.L : (k >= p.ms ? p.L : 0.0);
+        kk[a] = k < 0 ? k + p.ms : (k >= p.ms ? k - p.ms : k);
+      } else {      // u, w: no neighbour beyond the lattice
+        use = use && k >= 0 && k < p.mv;
+        kk[a] = k;
       }
-      kk[a] = k;
     }
-    if (!ok) continue;
+    if (!use) continue;
     const int m = ((kk[3] * p.mv + kk[2]) * p.ms + kk[1]) * p.ms + kk[0];
     double ex[4];
     map4(p, rec + (size_t)m * RS, P, ex);
     const double wgt = Wk(2.0 * sqrt(dist2(p, ex)));
     sw += wgt;
     for (int a = 0; a < 4; ++a) {
-      const double Qa = (lat_q(p, a, kk[a]) + shift[a]) + ex[a];
+      const double Qa = (lat_q(p, a, kk[a]) + (a < 2 ? shift[a] : 0.0)) + ex[a];
       sq[a] = fma(wgt, Qa, sq[a]);
     }
   }
