@@ -584,7 +584,12 @@ __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
     const double dqv = fma(r[R_AVX], ux, fma(r[R_AVV], uv, lv));
     const double zx = dqx * p.rx, zv = dqv * p.rv;
     const double d2 = fma(zx, zx, zv * zv);
-    if (d2 < bd || (d2 == bd && e < best)) {
+    // (d2, id) order; an exact tie of d2 is rare, so the id comparison is
+    // made only when some lane of the wavefront has one
+    bool upd = d2 < bd;
+    const bool tie = d2 == bd;
+    if (__builtin_expect(__ballot(tie) != 0ull, 0)) upd = upd || (tie && e < best);
+    if (upd) {
       bd = d2;
       best = e;
       bdqx = dqx;
@@ -689,12 +694,17 @@ __device__ __forceinline__ int query_block(
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int k = 0; k < m; ++k) {
-        const int e = __builtin_amdgcn_readlane(myid, k);
-        Rec r;
+      // unrolled: the record offsets are immediate and the ids scalar
+      // loads of the (uniform) list row
 #pragma unroll
-        for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
-        query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
+      for (int k = 0; k < QSTAGE; ++k) {
+        if (k < m) {
+          const int e = L[c0 + k];
+          Rec r;
+#pragma unroll
+          for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
+          query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
