@@ -640,6 +640,7 @@ __device__ __forceinline__ void load_rec(const double *__restrict__ rec,
 }
 
 // Records staged per round in a wavefront's LDS area (QSTAGE * RS doubles).
+typedef __attribute__((address_space(3))) void lds_void;
 constexpr int QSTAGE = 20;
 constexpr int RPIECES = RS / 2;  // 16-byte pieces per record
 
@@ -651,64 +652,88 @@ __device__ __forceinline__ int list_head(const KP &p, const int *L) {
   return (lane < min(p.cap, QSTAGE)) ? L[lane] : 0;
 }
 
+// Records c0 .. c0 + m - 1 of a block list (m <= QSTAGE) into a wave's LDS
+// area: pieces lane and lane + 64 (QSTAGE * RPIECES <= 128), loaded straight
+// into the area (a global-to-LDS load puts lane t's 16 bytes at the area's
+// start + 16 t).  Only issues the loads; stage_wait completes them.  id0
+// holds the list's first entries (lane-indexed), used for c0 == 0.
+__device__ __forceinline__ void stage_issue(const double *__restrict__ rec,
+                                            const int *__restrict__ L, int id0,
+                                            int c0, int m, double *stage) {
+  static_assert(QSTAGE * RPIECES <= 128, "two pieces per lane");
+  const int lane = threadIdx.x & 63;
+  const int myid = (lane < m) ? (c0 == 0 ? id0 : L[c0 + lane]) : 0;
+  const int np = m * RPIECES;
+  const int ta = lane, tb = lane + 64;
+  const int ra = ta / RPIECES, rb = tb / RPIECES;
+  const int ida = __shfl(myid, ra), idb = __shfl(myid, min(rb, 63));
+  if (ta < np)
+    __builtin_amdgcn_global_load_lds(
+        rec + (size_t)ida * RS + 2 * (ta - ra * RPIECES), (lds_void *)stage,
+        16, 0, 0);
+  if (tb < np)
+    __builtin_amdgcn_global_load_lds(
+        rec + (size_t)idb * RS + 2 * (tb - rb * RPIECES),
+        (lds_void *)(stage + 128), 16, 0, 0);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Every outstanding vector memory operation of the wave (the staging loads
+// among them) complete, the area readable by all lanes.
+__device__ __forceinline__ void stage_wait() {
+  __builtin_amdgcn_s_waitcnt(0);
+  wave_sync();
+}
+
+// The candidates of one staged round, unrolled: the record offsets are
+// immediate and the ids scalar loads of the (uniform) list row.
+template <int PER>
+__device__ __forceinline__ void query_round(
+    const KP &p, const int *__restrict__ L, int c0, int m, const double *stage,
+    double xP, double vP, double &bd, int &best, double &dqx, double &dqv) {
+#pragma unroll
+  for (int k = 0; k < QSTAGE; ++k) {
+    if (k < m) {
+      const int e = L[c0 + k];
+      Rec r;
+#pragma unroll
+      for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
+      query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
+    }
+  }
+}
+
 // Nearest element of (xP, vP) from the wave's block list, or from all
 // elements when the list overflowed or an element was too wide to list.
-// The list's records are brought into the wave's LDS area together (one
-// 16-byte piece per lane, about ten records per load instruction), so the
+// The list's records are brought into the wave's LDS area together, so the
 // candidates cost one memory round trip per QSTAGE records instead of one
 // each; the candidate loop then reads them as uniform LDS broadcasts.
 // L is the block's list row, id0 its first entries (lane-indexed, loaded by
-// the caller together with the count n).
+// the caller together with the count n).  With staged0, the caller has
+// already issued and waited for the first round (stage_issue, stage_wait).
 template <int PER>
 __device__ __forceinline__ int query_block(
     const KP &p, const double *__restrict__ rec, const int *__restrict__ L,
     int id0, int n, bool scan_all, double xP, double vP, double &dqx,
-    double &dqv, double *stage) {
+    double &dqv, double *stage, bool staged0 = false) {
   double bd = __builtin_inf();
   int best = -1;
   dqx = 0.0;
   dqv = 0.0;
-  const int lane = threadIdx.x & 63;
   if (!scan_all) {
     for (int c0 = 0; c0 < n; c0 += QSTAGE) {
       const int m = min(QSTAGE, n - c0);
-      const int myid = (lane < m) ? (c0 == 0 ? id0 : L[c0 + lane]) : 0;
-      // pieces lane and lane + 64 (QSTAGE * RPIECES <= 128): both loads
-      // are issued before either is stored
-      static_assert(QSTAGE * RPIECES <= 128, "two pieces per lane");
-      const int np = m * RPIECES;
-      const int ta = lane, tb = lane + 64;
-      const int ra = ta / RPIECES, rb = tb / RPIECES;
-      const int ida = __shfl(myid, ra), idb = __shfl(myid, min(rb, 63));
-      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-      if (ta < np)
-        va = *reinterpret_cast<const double2 *>(rec + (size_t)ida * RS +
-                                                2 * (ta - ra * RPIECES));
-      if (tb < np)
-        vb = *reinterpret_cast<const double2 *>(rec + (size_t)idb * RS +
-                                                2 * (tb - rb * RPIECES));
-      if (ta < np)
-        *reinterpret_cast<double2 *>(stage + 2 * ta) = va;
-      if (tb < np)
-        *reinterpret_cast<double2 *>(stage + 2 * tb) = vb;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // unrolled: the record offsets are immediate and the ids scalar
-      // loads of the (uniform) list row
-#pragma unroll
-      for (int k = 0; k < QSTAGE; ++k) {
-        if (k < m) {
-          const int e = L[c0 + k];
-          Rec r;
-#pragma unroll
-          for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
-          query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
-        }
+      if (!(staged0 && c0 == 0)) {
+        stage_issue(rec, L, id0, c0, m, stage);
+        stage_wait();
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      query_round<PER>(p, L, c0, m, stage, xP, vP, bd, best, dqx, dqv);
+      wave_sync();
     }
   } else {
     for (int e = 0; e < p.E; ++e) {
