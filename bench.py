@@ -52,6 +52,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+WARM_S = 0.5                    # least seconds of warm-up per timed run
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, FMA counted as 2
 FLOPS_PER_EVAL = 34             # one full candidate evaluation, FP64
 EVALS_PER_SITE = 4              # windows holding a site (2 per axis)
@@ -96,7 +97,15 @@ def run_gpu(precision: str, cfg, f0, steps: int, warmup: int, **extra):
     f0t = torch.as_tensor(f0, device="cuda:0")
     run.init_conditions(f0t)
     if warmup:
+        # the warm-up steps, repeated until the device has been busy for
+        # WARM_S seconds: its clocks rise under sustained load, and the
+        # first leg measured would otherwise run partly before they have
+        t_w = time.perf_counter()
         run.step(warmup)
+        torch.cuda.synchronize()
+        while time.perf_counter() - t_w < WARM_S:
+            run.step(warmup)
+            torch.cuda.synchronize()
     out = {}
     for prof in (False, True):
         run.init_conditions(f0t)        # timed region = the run from t = 0
