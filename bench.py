@@ -490,6 +490,34 @@ def cpu_baseline(cfg, f0, steps: int, threads: int, single_steps: int):
     return out
 
 
+def cpu_baseline_large(threads: int, plan=(("c3_halos_sheet_8192", 2),
+                                            ("c5_halos_cold_16384", 1))):
+    """The oracle on the host (`threads` OpenMP threads) over a short prefix
+    of each large workload from t = 0 (bounded so that the default run stays
+    within minutes): site updates/s, to set beside the GPU rates of the
+    large-grid leg.  The initial condition (spline fit of F_ini) is not
+    timed."""
+    import oracle
+    import workloads as W
+    out = {}
+    used = oracle.set_threads(threads)
+    for name, nst in plan:
+        cfg, f0 = W.config(name)
+        p = cfg.params()
+        p.pop("precision")
+        o = oracle.Oracle(**p)
+        o.init_conditions(f0)
+        del f0
+        t0 = time.perf_counter()
+        o.step(nst)
+        dt = time.perf_counter() - t0
+        out[name] = {"value": cfg.n * cfg.n * nst / dt,
+                     "unit": "site updates/s", "cores": used, "steps": nst,
+                     "seconds": dt, "kind": "oracle"}
+        del o
+    return out
+
+
 def serve_leg(count: int, step_scale: float, seed: int, occupancy: float,
               max_active: int, pool_gb: float, tol: float = 0.05,
               max_passes: int = 3):
@@ -780,6 +808,13 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg, f0, args.cpu_steps,
                                            args.cpu_threads,
                                            args.cpu_single_steps)
+        if args.only is None:
+            out["cpu_baseline"]["large_grids"] = cpu_baseline_large(
+                args.cpu_threads)
+            for k, v in out["cpu_baseline"]["large_grids"].items():
+                print(f"[bench] oracle on the host, {k}: {v['value']:.3e} "
+                      f"site updates/s ({v['steps']} steps, "
+                      f"{v['seconds']:.1f} s)", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 
