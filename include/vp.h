@@ -46,8 +46,8 @@
  *
  * Errors: every call returns a status.  No exception crosses the ABI.
  *   VP_OK 0, VP_EINVAL -1 (bad argument or parameters), VP_ENOMEM -2
- *   (workspace too small), VP_EDEVICE -3 (HIP error, or a grid-wide wait of
- *   the element pass that timed out; text in vp_last_error), VP_ESTATE -4
+ *   (workspace too small), VP_EDEVICE -3 (HIP error; text in
+ *   vp_last_error), VP_ESTATE -4
  *   (call before vp_init_conditions), VP_ENUMERIC -5 (a non-finite element
  *   or det T <= 0 met on the device).  Conditions found on the device are
  *   reported by the next synchronising call: vp_sync, vp_diagnostics.

@@ -2,11 +2,11 @@
 // sequencing on the caller's stream, and the C ABI declared in vp.h.
 //
 // Every step runs k_recon (nearest element, inverse map, six-point
-// interpolation, row-group column partials) and then the element pass:
-// k_elem_field_coop on grids of at most 2048 columns (column sums,
-// cumulative mass and force, then TSC, kick, corrector drift, the next
-// predictor drift, A = T^-1 and the query-block lists), else k_field and
-// k_field_tail (the field) followed by k_elem.  A run's first step, and
+// interpolation, row-group column partials) and then the element pass: on
+// grids of at most 2048 columns k_field_chunks (column sums, chunks of the
+// cumulative mass) and k_elem_window (carries and force, then TSC, kick,
+// corrector drift, the next predictor drift, A = T^-1 and the query-block
+// lists), else k_field and k_field_tail (the field) followed by k_elem.  A run's first step, and
 // the first after a resampling, starts with k_elem (predictor and lists).
 // Every n_s steps the resampling: k_remap_eval, the spline fit (k_fit_x or
 // k_fit_x_cyclic, k_fit_v, ghosts) on a second stream beside the following
@@ -38,7 +38,7 @@ namespace {
 thread_local std::string g_create_error;
 
 struct Layout {
-  size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, fcnt, fsync, Mc, ctot,
+  size_t F, C, T, st, rec, qm, cnt, lst, flags, ovf, part, fcnt, Mc, ctot,
       rmx, clk, Ml, acc,
       dpart, dout, tab, total;
   size_t fbytes;  // bytes per f value
@@ -151,7 +151,6 @@ Layout make_layout(const vp_params *p, const KP &k) {
   L.ovf = take(64);
   L.part = take((size_t)k.ngy * k.nx * 8);
   L.fcnt = take(64);
-  L.fsync = take(64);
   L.Mc = take((size_t)k.nx * 8);
   L.ctot = take((size_t)FIELD_CHUNKS * 8);
   L.rmx = take((size_t)FIELD_CHUNKS * 8);  // per-chunk / per-workgroup rho max
@@ -190,8 +189,6 @@ struct vp_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_eval = nullptr, ev_fit = nullptr;
   bool fit_pending = false;
-  int coop_grid = 0;     // largest co-resident grid of k_elem_field_coop
-  int64_t fsync_target = 0;  // chunks published so far through L.fsync
   int64_t reset_step = 0;  // step of the elements' last reset
   std::string err;
   std::vector<char> host_tab;  // source of the pivot-table upload
@@ -274,56 +271,30 @@ int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
 }
 
 // Field from the reconstruction's partials + kick + corrector (+ next
-// predictor) in one launch (grids of at most FIELD1_MAX columns).  Where
-// the whole grid fits on the device at once, the shared form computes the
-// field once (its producers are the lowest workgroups, which wait on
-// nothing, so they run first whatever the residency; the consumers' wait is
-// bounded); otherwise every workgroup rebuilds the field.
+// predictor) for grids of at most FIELD1_MAX columns: the chunks of the
+// cumulative mass (k_field_chunks, one wavefront per 64 columns), then the
+// element pass that takes its force from them (k_elem_window).
 int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
                       int zero_buf) {
   KP k = c->k;
   k.par ^= 1;  // completes the previous step (see launch_elem)
   ProfScope ps(c, PK_KICK);
-  const long long nbz = c->L.nb;
   const int nch = (k.nx + MCHUNK - 1) / MCHUNK;
-  // one workgroup per element patch, at least one per field chunk
-  const int grid = std::max(elem_patches(k.mx, k.mv), nch);
-  const long long n =
-      std::max<long long>(k.E, std::min<long long>(nbz, 1 << 22));
-  if (grid <= c->coop_grid) {
-    int *fsync = c->at<int>(c->L.fsync);
-    if (c->fsync_target + nch > (1 << 30)) {
-      hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(256), 0, c->stream,
-                         fsync, 1LL, 0);
-      VP_LAUNCH_CHECK(c, "k_fill");
-      c->fsync_target = 0;
-    }
-    c->fsync_target += nch;
-    KP kk = k;
-    const double *part = c->at<double>(c->L.part);
-    double *Mc = c->at<double>(c->L.Mc), *ctot = c->at<double>(c->L.ctot),
-           *cmax = c->at<double>(c->L.rmx);
-    int target = (int)c->fsync_target;
-    double *st = c->at<double>(c->L.st), *rec = c->at<double>(c->L.rec),
-           *qm = c->at<double>(c->L.qm);
-    int *cz = c->counts(zero_buf), *cr = c->counts(reg_buf);
-    long long nb = nbz;
-    int *lst = c->at<int>(c->L.lst), *flags = c->at<int>(c->L.flags);
-    hipLaunchKernelGGL(k_elem_field_coop, dim3(grid), dim3(ELEMC_WG), 0,
-                       c->stream, kk, part, Mc, ctot, cmax, fsync, target, st,
-                       rec,
-                       qm, cz, nb, cr, lst, flags, predict, reg);
-    VP_LAUNCH_CHECK(c, "k_elem_field_coop");
-    return VP_OK;
-  }
-  hipLaunchKernelGGL(k_elem_field, dim3(grid_for(n, ELEMF_WG)),
-                     dim3(ELEMF_WG), 0, c->stream, k,
-                     c->at<double>(c->L.part), c->at<double>(c->L.st),
-                     c->at<double>(c->L.rec), c->at<double>(c->L.qm),
-                     c->counts(zero_buf), nbz, c->counts(reg_buf),
-                     c->at<int>(c->L.lst), c->at<int>(c->L.flags), predict,
-                     reg);
-  VP_LAUNCH_CHECK(c, "k_elem_field");
+  const double *part = c->at<double>(c->L.part);
+  double *Mc = c->at<double>(c->L.Mc), *ctot = c->at<double>(c->L.ctot),
+         *cmax = c->at<double>(c->L.rmx);
+  hipLaunchKernelGGL(k_field_chunks, dim3(nch), dim3(64), 0, c->stream, k,
+                     part, Mc, ctot, cmax);
+  VP_LAUNCH_CHECK(c, "k_field_chunks");
+  double *st = c->at<double>(c->L.st), *rec = c->at<double>(c->L.rec),
+         *qm = c->at<double>(c->L.qm);
+  int *cz = c->counts(zero_buf), *cr = c->counts(reg_buf);
+  const long long nb = c->L.nb;
+  int *lst = c->at<int>(c->L.lst), *flags = c->at<int>(c->L.flags);
+  hipLaunchKernelGGL(k_elem_window, dim3(elem_patches(k.mx, k.mv)),
+                     dim3(ELEMC_WG), 0, c->stream, k, Mc, ctot, cmax, st, rec,
+                     qm, cz, nb, cr, lst, flags, predict, reg);
+  VP_LAUNCH_CHECK(c, "k_elem_window");
   return VP_OK;
 }
 
@@ -818,10 +789,6 @@ int check_flags(vp_ctx *c) {
     c->err = "non-finite element state or det T <= 0 met on the device";
     return VP_ENUMERIC;
   }
-  if (flags & FLAG_SYNC) {
-    c->err = "grid-wide wait of the element pass timed out";
-    return VP_EDEVICE;
-  }
   return VP_OK;
 }
 
@@ -871,17 +838,6 @@ int vp_create(const vp_params *p, void *dev_workspace, size_t bytes,
   c->t = 0.0;
   c->step = 0;
   c->ready = false;
-  // the shared-field element pass: the largest grid that is resident at once
-  {
-    int dev = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
-                              dev) == hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_elem_field_coop),
-            ELEMC_WG, 0) == hipSuccess)
-      c->coop_grid = per_cu * ncu;
-  }
   // zero the whole workspace once (F padding, counts, flags, counters), then
   // the spline pivot tables and the initial elements
   int rc = fill<int>(c, c->at<int>(0), (long long)(L.total / 4), 0);

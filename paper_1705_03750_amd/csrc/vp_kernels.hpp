@@ -41,7 +41,7 @@ enum {
   S_X = 0, S_V, S_TXX, S_TXV, S_TVX, S_TVV, S_HXXX, S_HXXV, S_HXVV, S_HVXX,
   S_HVXV, S_HVVV, NSTATE
 };
-enum { FLAG_NUMERIC = 1, FLAG_WIDE = 2, FLAG_SYNC = 4 };
+enum { FLAG_NUMERIC = 1, FLAG_WIDE = 2 };
 enum { MODE_DENSITY = 0, MODE_F = 1, MODE_ASSIGN = 2, MODE_DIAG = 3,
        MODE_EMAP = 4 };  // MODE_EMAP: the E_map maximum of MODE_DIAG alone
 // Per-workgroup diagnostic partials of MODE_DIAG: sum v^2 f, sum f ln|f|,
@@ -1008,25 +1008,22 @@ struct AccFromMass {
 // The same force for one element without the whole M_left table (isolated
 // x): the six cumulative masses M_left(i0 - 3 .. i0 + 2) that the dual TSC
 // around site i0 needs, each the carry of its 64-site chunk plus the
-// chunk's published prefix, give a at i0 - 2 .. i0 + 2 and then a, a', a''
-// at i0 - 1 .. i0 + 1 with the operations of acc_site and acc_from_mass
-// (the same values bit for bit).
+// chunk's own prefix (mw, read beforehand), give a at i0 - 2 .. i0 + 2 and
+// then a, a', a'' at i0 - 1 .. i0 + 1 with the operations of acc_site and
+// acc_from_mass (the same values bit for bit).
 struct AccWindow {
   const KP &p;
   double a[5];  // a at sites i0 - 2 .. i0 + 2
   int q0;       // table index i0 + 4 of site i0
   __device__ __forceinline__ AccWindow(const KP &p_, int i0,
-                                       const double *car,
-                                       const double *__restrict__ Mc,
+                                       const double *car, const double *mw,
                                        double Mtot)
       : p(p_), q0(i0 + 4) {
     double m[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
       const int j = i0 - 3 + d;
-      m[d] = (j < 0) ? 0.0
-             : (j >= p.nx) ? Mtot
-                           : car[j / MCHUNK] + ld_coherent(Mc + j);
+      m[d] = (j < 0) ? 0.0 : (j >= p.nx) ? Mtot : car[j / MCHUNK] + mw[d];
     }
 #pragma unroll
     for (int d = 0; d < 5; ++d) a[d] = p.G * ((Mtot - m[d + 1]) - m[d]);
@@ -1383,62 +1380,71 @@ __device__ __forceinline__ double elem_clock(KP &p, double rmax, int predict,
   return dtn;
 }
 
-// Field and element pass in one launch (grids of at most FIELD1_MAX
-// columns, self-consistent force): every workgroup rebuilds M_left from
-// the reconstruction's row-group partials in LDS (the partials stay in L2;
-// the same operations as the field kernel, so the force is bit-identical),
-// then kicks its elements with it; the rest is k_elem's pass.  Replaces a
-// launch whose single workgroup would leave the GPU idle.
-constexpr int ELEMF_WG = 512;
-
-__global__ __launch_bounds__(ELEMF_WG) void k_elem_field(
-    KP p, const double *__restrict__ part, double *__restrict__ st,
-    double *__restrict__ rec, double *__restrict__ qm,
-    int *__restrict__ cnt_zero, long long nb_zero,
-    int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
-    int predict, int reg) {
-  __shared__ double M[FIELD1_MAX];
-  __shared__ double car[FIELD1_MAX / MCHUNK + 1];
-  __shared__ double red[ELEMF_WG / 64];
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long gsz = (long long)gridDim.x * blockDim.x;
-  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
-  const int e = (int)gid;
-  const size_t E = (size_t)p.E;
-  ElemState s;
-  if (e < p.E) elem_load(st, E, e, s);  // in flight during the field
-  double rmax = 0.0;
-  const double Mtot = mass_to_lds<ELEMF_WG>(p, part, p.ngy, 0, nullptr, M,
-                                            car, red, rmax);
-  const double Bbar = p.per ? periodic_mean<ELEMF_WG>(p, M, Mtot, car) : 0.0;
-  const double dtn = elem_clock(p, rmax, predict, gid == 0);
-  if (e >= p.E) return;
-  elem_kick(p, AccFromMass{p, M, Mtot, Bbar}, s);
-  if (predict) {
-    p.h = 0.5 * dtn;
-    elem_drift(p, s);
+// Chunk c of the cumulative mass (one wavefront, one lane per column): the
+// column sums of the reconstruction's row-group partials in increasing group
+// order, rho, the chunk's sequential running sum of dx rho (Mc, the chunk's
+// own prefix), its total (ctot) and, with the variable step, its largest
+// density (cmax).  M holds MCHUNK doubles of LDS.
+__device__ __forceinline__ void field_chunk_publish(
+    const KP &p, const double *__restrict__ part, double *__restrict__ Mc,
+    double *__restrict__ ctot, double *__restrict__ cmax, int c, double *M) {
+  const int tid = threadIdx.x & 63, nx = p.nx;
+  const int i0 = c * MCHUNK, n = min(MCHUNK, nx - i0);
+  double m = 0.0;
+  if (tid < n) {
+    const int i = i0 + tid;
+    double x = 0.0;
+    // every row group's partial requested at once (one memory round trip
+    // for grids up to 40 groups), then added in increasing group order
+    for (int g0 = 0; g0 < p.ngy; g0 += 40) {
+      double v[40];
+#pragma unroll
+      for (int u = 0; u < 40; ++u)
+        v[u] = (g0 + u < p.ngy) ? part[(size_t)(g0 + u) * nx + i] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 40; ++u)
+        if (g0 + u < p.ngy) x += v[u];
+    }
+    const double rho = p.dv * x;
+    M[tid] = p.dx * rho;
+    m = fmax(m, rho);
   }
-  elem_store(st, E, e, s);
-  if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
+  if (p.clk) {
+    // the chunk's largest density, published with the chunk
+    m = wave_max(m);
+    if (tid == 0) cmax[c] = m;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (tid == 0) ctot[c] = seq_prefix(M, n);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (tid < n) Mc[i0 + tid] = M[tid];
 }
 
-// The same pass with the field shared instead of recomputed: the first
-// nch workgroups each sum one 64-column chunk (column sums in increasing
-// group order, the chunk's sequential prefix and total) and publish it;
-// after a grid-wide wait every workgroup adds the carries sequentially and
-// takes M_left from the published chunks (the whole table with periodic x,
-// else the six values around each element's TSC cell).  The producers are
-// the lowest-numbered workgroups and wait on nothing, so in-order dispatch
-// runs them first; the grid is launched only when it fits on the device at
-// once, and the wait is bounded (FLAG_SYNC instead of a hang).  fsync
-// counts published chunks over the run's lifetime; this launch waits for
-// target.
-constexpr int SYNC_SPIN_LIMIT = 1 << 20;  // about a second
+// The chunks of the cumulative mass as a launch of their own (one
+// wavefront per chunk), for the element pass that follows it on the stream.
+__global__ __launch_bounds__(64) void k_field_chunks(
+    KP p, const double *__restrict__ part, double *__restrict__ Mc,
+    double *__restrict__ ctot, double *__restrict__ cmax) {
+  __shared__ double M[MCHUNK];
+  field_chunk_publish(p, part, Mc, ctot, cmax, blockIdx.x, M);
+}
+
+// Field and element pass of a step (grids of at most FIELD1_MAX columns,
+// self-consistent force), launched after k_field_chunks on the same stream:
+// every workgroup adds the chunk totals sequentially into carries and takes
+// M_left from the chunks (the whole table with periodic x, else the six
+// values around each element's TSC cell), then kicks, corrects, predicts
+// and registers its elements.  Every load the field needs is issued in one
+// round trip together with the element state.
 constexpr int ELEMC_WG = 256;
-// Elements of the shared-field pass come in PATCH x PATCH lattice patches,
-// one per workgroup: the block lists an element registers into are mostly
-// those of its neighbours in the same workgroup, which keeps the slot
-// claims of a workgroup on few cache lines of the counts.
+// Elements come in PATCH x PATCH lattice patches, one per workgroup: the
+// block lists an element registers into are mostly those of its neighbours
+// in the same workgroup, which keeps the slot claims of a workgroup on few
+// cache lines of the counts.
 constexpr int PATCH = 16;
 static_assert(PATCH * PATCH == ELEMC_WG, "one element per thread");
 
@@ -1447,17 +1453,14 @@ __host__ __device__ __forceinline__ int elem_patches(int mx, int mv) {
   return ((mx + PATCH - 1) / PATCH) * ((mv + PATCH - 1) / PATCH);
 }
 
-__global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
-    KP p, const double *__restrict__ part, double *__restrict__ Mc,
-    double *__restrict__ ctot, double *__restrict__ cmax,
-    int *__restrict__ fsync, int target,
-    double *__restrict__ st, double *__restrict__ rec,
-    double *__restrict__ qm, int *__restrict__ cnt_zero, long long nb_zero,
-    int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
-    int predict, int reg) {
+__global__ __launch_bounds__(ELEMC_WG) void k_elem_window(
+    KP p, const double *__restrict__ Mc, const double *__restrict__ ctot,
+    const double *__restrict__ cmax, double *__restrict__ st,
+    double *__restrict__ rec, double *__restrict__ qm,
+    int *__restrict__ cnt_zero, long long nb_zero, int *__restrict__ cnt_reg,
+    int *__restrict__ lst, int *__restrict__ flags, int predict, int reg) {
   __shared__ double M[FIELD1_MAX];
   __shared__ double car[FIELD1_MAX / MCHUNK + 1];
-  __shared__ int s_ok;
   __shared__ double s_rmax, s_mtot;
   const int tid = threadIdx.x, nx = p.nx;
   const int nch = (nx + MCHUNK - 1) / MCHUNK;
@@ -1472,81 +1475,38 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
   const int e = has ? el * p.mx + ek : 0;
   const size_t E = (size_t)p.E;
   ElemState s;
-  if (has) elem_load(st, E, e, s);  // in flight during the field
-  const int c = blockIdx.x;
-  if (c < nch && tid < 64) {
-    // chunk c: one lane per column
-    const int i0 = c * MCHUNK, n = min(MCHUNK, nx - i0);
-    double m = 0.0;
-    if (tid < n) {
-      const int i = i0 + tid;
-      double x = 0.0;
-      // every row group's partial requested at once (one memory round trip
-      // for grids up to 40 groups), then added in increasing group order
-      for (int g0 = 0; g0 < p.ngy; g0 += 40) {
-        double v[40];
-#pragma unroll
-        for (int u = 0; u < 40; ++u)
-          v[u] = (g0 + u < p.ngy) ? part[(size_t)(g0 + u) * nx + i] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 40; ++u)
-          if (g0 + u < p.ngy) x += v[u];
-      }
-      const double rho = p.dv * x;
-      M[tid] = p.dx * rho;
-      m = fmax(m, rho);
-    }
-    if (p.clk) {
-      // the chunk's largest density, published with the chunk
-      m = wave_max(m);
-      if (tid == 0) cmax[c] = m;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (tid == 0) ctot[c] = seq_prefix(M, n);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (tid < n) Mc[i0 + tid] = M[tid];
-    // one wavefront published the chunk: release it to the grid
-    if (tid == 0)
-      __hip_atomic_fetch_add(fsync, 1, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
+  if (has) elem_load(st, E, e, s);
+  // one lane per chunk: the totals, the last prefix and the chunk maxima
+  double ct = 0.0, cm = 0.0, mlast = 0.0;
+  if (tid < nch) {
+    ct = ctot[tid];
+    if (p.clk) cm = cmax[tid];
   }
-  if (tid == 0) {
-    int ok = 1, spins = 0;
-    while (__hip_atomic_load(fsync, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > SYNC_SPIN_LIMIT) {
-        ok = 0;
-        break;
-      }
+  if (tid == 0) mlast = Mc[nx - 1];
+  // isolated x: the six chunk prefixes around the element's TSC cell
+  double mw[6];
+  int i0 = 0;
+  if (has && !p.per) {
+    double w;
+    i0 = (int)tsc_cell(p, s.x, w);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const int j = i0 - 3 + d;
+      mw[d] = (j >= 0 && j < nx) ? Mc[j] : 0.0;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!ok) atomicOr(flags, FLAG_SYNC);
-    s_ok = ok;
   }
-  __syncthreads();
-  // the previous lists' counts are cleared only now: stores made before the
-  // producers' release would be written back with it
-  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
-  // carries from the published chunk totals (one lane per chunk, the
-  // sequential sum across the lanes); with periodic x the whole M_left
-  // table (the mean of B needs every site), else each element reads the six
-  // chunk prefixes around its TSC cell (AccWindow)
+  // periodic x: the whole table (the mean of B needs every site)
   if (p.per)
-    for (int i = tid; i < nx; i += ELEMC_WG) M[i] = ld_coherent(Mc + i);
+    for (int i = tid; i < nx; i += ELEMC_WG) M[i] = Mc[i];
+  // the counts of the lists the reconstruction has just used, for the next
+  // element pass
+  for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
   if (tid < 64) {
-    // one lane per chunk: totals, the last prefix and the chunk maxima in
-    // one round trip
-    if (tid < nch) car[tid] = ld_coherent(ctot + tid);
-    if (tid == 0) s_mtot = ld_coherent(Mc + nx - 1);
-    double m = (p.clk && tid < nch) ? ld_coherent(cmax + tid) : 0.0;
+    if (tid < nch) car[tid] = ct;
+    if (tid == 0) s_mtot = mlast;
     if (p.clk) {
-      m = wave_max(m);
-      if (tid == 0) s_rmax = m;
+      cm = wave_max(cm);
+      if (tid == 0) s_rmax = cm;
     }
   }
   __syncthreads();
@@ -1570,15 +1530,17 @@ __global__ __launch_bounds__(ELEMC_WG) void k_elem_field_coop(
   } else {
     Mtot = s_mtot;
   }
-  if (!s_ok) return;
   const double dtn = elem_clock(p, p.clk ? s_rmax : 0.0, predict, gid == 0);
   if (has) {
-    if (p.per || p.force_mode != 0) {
+    if (p.per)
       elem_kick(p, AccFromMass{p, M, Mtot, Bbar}, s);
-    } else {
+    else {
+      // the cell again, from the same x (equal to i0): the kick's own
+      // tsc_cell then matches it at compile time, and the window's offsets
+      // stay constants
       double w;
-      const int i0 = (int)tsc_cell(p, s.x, w);
-      elem_kick(p, AccWindow(p, i0, car, Mc, Mtot), s);
+      const int ic = (int)tsc_cell(p, s.x, w);
+      elem_kick(p, AccWindow(p, ic, car, mw, Mtot), s);
     }
     if (predict) {
       p.h = 0.5 * dtn;
