@@ -105,6 +105,13 @@ KP make_kp(const vp_params *p) {
   k.dvm = p->sv * k.dv;
   k.rx = 1.0 / k.dxm;
   k.rv = 1.0 / k.dvm;
+  {
+    // equal powers of two well inside the normal range: the query may then
+    // rank candidates by the unscaled squared offset (the same order)
+    int ex = 0;
+    const double mant = std::frexp(k.rx, &ex);
+    k.r2 = (k.rx == k.rv && mant == 0.5 && ex > -400 && ex < 400) ? 1 : 0;
+  }
   k.G = p->G;
   k.dt = p->dt;
   k.h = 0.5 * p->dt;

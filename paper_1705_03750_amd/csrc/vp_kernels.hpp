@@ -67,6 +67,9 @@ struct KP {
   // last block column of a row group being one block split by the seam.
   int per, nbl;
   double Lx, hL, x_max;
+  // rx == rv, a power of two: the query ranks candidates by the unscaled
+  // squared offset, which is the scaled one divided by rx^2 exactly
+  int r2;
 };
 
 // Periodic x: a position moved out of [x_min, x_max) by a drift re-enters
@@ -567,8 +570,10 @@ __global__ __launch_bounds__(256) void k_fill(T *__restrict__ a, long long n,
 // is the smallest (d^2, id).  r is the candidate's record.  With -H/2 in
 // the record, dQ = l + A u' with u'_c = l^T (-H_c/2) l, which equals
 // l - A u / 2 bit for bit (scaling by a power of two commutes with every
-// rounding step).
-template <int PER, typename R>
+// rounding step).  With R2 (rx == rv == r, a power of two) d^2 is ranked
+// as |dQ|^2 = d^2 / r^2: the same scaling argument makes the two orders
+// (and their ties) identical.
+template <int PER, bool R2, typename R>
 __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
                                                 double xP, double vP,
                                                 double &bd, int &best,
@@ -582,8 +587,13 @@ __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
     const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
     const double dqx = fma(r[R_AXX], ux, fma(r[R_AXV], uv, lx));
     const double dqv = fma(r[R_AVX], ux, fma(r[R_AVV], uv, lv));
-    const double zx = dqx * p.rx, zv = dqv * p.rv;
-    const double d2 = fma(zx, zx, zv * zv);
+    double d2;
+    if (R2) {
+      d2 = fma(dqx, dqx, dqv * dqv);
+    } else {
+      const double zx = dqx * p.rx, zv = dqv * p.rv;
+      d2 = fma(zx, zx, zv * zv);
+    }
     // (d2, id) order; an exact tie of d2 is rare, so the id comparison is
     // made only when some lane of the wavefront has one
     bool upd = d2 < bd;
@@ -692,7 +702,7 @@ __device__ __forceinline__ void stage_wait() {
 
 // The candidates of one staged round, unrolled: the record offsets are
 // immediate and the ids scalar loads of the (uniform) list row.
-template <int PER>
+template <int PER, bool R2>
 __device__ __forceinline__ void query_round(
     const KP &p, const int *__restrict__ L, int c0, int m, const double *stage,
     double xP, double vP, double &bd, int &best, double &dqx, double &dqv) {
@@ -703,7 +713,7 @@ __device__ __forceinline__ void query_round(
       Rec r;
 #pragma unroll
       for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
-      query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
+      query_candidate<PER, R2>(p, r, e, xP, vP, bd, best, dqx, dqv);
     }
   }
 }
@@ -716,11 +726,11 @@ __device__ __forceinline__ void query_round(
 // L is the block's list row, id0 its first entries (lane-indexed, loaded by
 // the caller together with the count n).  With staged0, the caller has
 // already issued and waited for the first round (stage_issue, stage_wait).
-template <int PER>
-__device__ __forceinline__ int query_block(
+template <int PER, bool R2>
+__device__ __forceinline__ int query_block_r(
     const KP &p, const double *__restrict__ rec, const int *__restrict__ L,
     int id0, int n, bool scan_all, double xP, double vP, double &dqx,
-    double &dqv, double *stage, bool staged0 = false) {
+    double &dqv, double *stage, bool staged0) {
   double bd = __builtin_inf();
   int best = -1;
   dqx = 0.0;
@@ -732,17 +742,28 @@ __device__ __forceinline__ int query_block(
         stage_issue(rec, L, id0, c0, m, stage);
         stage_wait();
       }
-      query_round<PER>(p, L, c0, m, stage, xP, vP, bd, best, dqx, dqv);
+      query_round<PER, R2>(p, L, c0, m, stage, xP, vP, bd, best, dqx, dqv);
       wave_sync();
     }
   } else {
     for (int e = 0; e < p.E; ++e) {
       Rec r;
       load_rec(rec, e, r);
-      query_candidate<PER>(p, r, e, xP, vP, bd, best, dqx, dqv);
+      query_candidate<PER, R2>(p, r, e, xP, vP, bd, best, dqx, dqv);
     }
   }
   return best;
+}
+
+template <int PER>
+__device__ __forceinline__ int query_block(
+    const KP &p, const double *__restrict__ rec, const int *__restrict__ L,
+    int id0, int n, bool scan_all, double xP, double vP, double &dqx,
+    double &dqv, double *stage, bool staged0 = false) {
+  return p.r2 ? query_block_r<PER, true>(p, rec, L, id0, n, scan_all, xP, vP,
+                                          dqx, dqv, stage, staged0)
+              : query_block_r<PER, false>(p, rec, L, id0, n, scan_all, xP, vP,
+                                           dqx, dqv, stage, staged0);
 }
 
 // ------------------------------------------------------- interpolations
