@@ -85,6 +85,7 @@ __global__ __launch_bounds__(256) void kb_elem(
     const RunDesc<FT> &R = runs[pi.slot];
     KP p = R.k;
     p.tau = 0.5 * p.dt * pi.h;
+    gox_set(p);
     const int arg = pi.arg;
     const long long idx = (long long)(item - pi.begin) * 256 + threadIdx.x;
     if (arg & EA_ZERO) {
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     const int bx = local % R.k.nbx, gy = local / R.k.nbx;
     KP p = R.k;
     p.tau = 0.5 * p.dt * pi.h;
+    gox_set(p);
     recon_tile<FT, MODE, 0>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
                          R.flags, R.F, R.part, R.fout, nullptr, R.dpart, R.ovf,
                          bx, gy);
@@ -177,6 +179,7 @@ __global__ __launch_bounds__(512) void kb_remap(
     const int bx = local % R.k.nbx, gy = local / R.k.nbx;
     KP p = R.k;
     p.tau = 0.5 * p.dt * pi.h;
+    gox_set(p);
     remap_tile<FT, 0, 0>(p, R.rec, R.qm, R.cnt + (pi.arg ? R.nb : 0), R.lst,
                       R.flags, R.C, R.F, R.ovf, bx, gy);
   }

@@ -112,6 +112,15 @@ KP make_kp(const vp_params *p) {
     const double mant = std::frexp(k.rx, &ex);
     k.r2 = (k.rx == k.rv && mant == 0.5 && ex > -400 && ex < 400) ? 1 : 0;
   }
+  // tile index t -> row group t / nbx as (t ceil(2^40 / nbx)) >> 40: exact
+  // for every t < nbx ngy when nbx^2 ngy < 2^40 (the rounding excess of the
+  // multiplier, below t / 2^40, then stays under 1 / nbx)
+  {
+    const unsigned long long nbx = (unsigned long long)k.nbx;
+    k.tdm = (nbx * nbx * (unsigned long long)k.ngy < (1ull << 40))
+                ? ((1ull << 40) + nbx - 1) / nbx
+                : 0ull;
+  }
   k.G = p->G;
   k.dt = p->dt;
   k.h = 0.5 * p->dt;
@@ -128,6 +137,7 @@ KP make_kp(const vp_params *p) {
   k.x_max = p->x_max;
   k.Lx = p->x_max - p->x_min;
   k.hL = 0.5 * k.Lx;
+  gox_set(k);
   return k;
 }
 
@@ -311,6 +321,7 @@ int launch_elem_field(vp_ctx *c, int predict, int reg, int reg_buf,
 void set_list_time(vp_ctx *c, bool half) {
   c->k.tau = ((double)(c->step - c->reset_step) + (half ? 0.5 : 0.0)) *
              c->p.dt;
+  gox_set(c->k);
 }
 
 // Records and block lists for the current element state (no motion).

@@ -70,7 +70,29 @@ struct KP {
   // rx == rv, a power of two: the query ranks candidates by the unscaled
   // squared offset, which is the scaled one divided by rx^2 exactly
   int r2;
+  // query-block x shift of the row groups at list time tau (gox_set)
+  long long goxA, goxB;
+  // ceil(2^40 / nbx) when it splits every tile index exactly, else 0
+  unsigned long long tdm;
 };
+
+// The drift at row group gy's central velocity since the elements' last
+// reset, in sites, is (goxB + gy goxA) / 2^32 (32.32 fixed point; zero for
+// a non-finite or huge drift).  Set wherever the list time is, so that the
+// block lists and the queries that read them take the same geometry.
+__host__ __device__ inline void gox_set(KP &p) {
+  const double a = 64.0 * p.dv * p.tau * p.inv_dx;
+  const double b =
+      (p.v_min + ((double)(p.ov - 64 * p.obv + 32) + 0.5) * p.dv) * p.tau *
+      p.inv_dx;
+  if (fabs(a) * (double)(p.ngy + 1) + fabs(b) < 1.0e6) {
+    p.goxA = llrint(a * 4294967296.0);
+    p.goxB = llrint(b * 4294967296.0);
+  } else {
+    p.goxA = 0;
+    p.goxB = 0;
+  }
+}
 
 // Periodic x: a position moved out of [x_min, x_max) by a drift re-enters
 // from the other side (one period at most; a sum that rounds onto x_max is
@@ -125,7 +147,10 @@ __device__ __forceinline__ double next_dt(const KP &p, double rho_max) {
 
 // List time of the current slot (kernels that read the block lists).
 __device__ __forceinline__ void clock_tau(KP &p) {
-  if (p.clk) p.tau = p.clk[CK_SLOT * p.par + CK_TAU];
+  if (p.clk) {
+    p.tau = p.clk[CK_SLOT * p.par + CK_TAU];
+    gox_set(p);
+  }
 }
 
 __device__ __forceinline__ double site_x(const KP &p, int i) {
@@ -153,10 +178,15 @@ __device__ __forceinline__ int group_of_brow(const KP &p, int bv) {
 // of the group covers columns [o + 8 (bx - 1), o + 8 bx).  Only the work
 // depends on this choice: lists and queries use the same geometry.
 __device__ __forceinline__ int group_ox(const KP &p, int gy) {
-  const double vc = site_v(p, p.ov + 64 * (gy - p.obv) + 32);
-  double d = vc * p.tau * p.inv_dx;
-  if (!(fabs(d) < 1.0e6)) d = 0.0;
-  return (p.ox + (int)ceil(d)) & 7;
+  const long long x = p.goxB + (long long)gy * p.goxA;
+  return (p.ox + (int)(-((-x) >> 32))) & 7;  // ceil(x / 2^32)
+}
+
+// Tile t of the reconstruction grid as (block column bx, row group gy).
+__device__ __forceinline__ void tile_split(const KP &p, int t, int &bx,
+                                           int &gy) {
+  gy = p.tdm ? (int)(((unsigned long long)t * p.tdm) >> 40) : t / p.nbx;
+  bx = t - gy * p.nbx;
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin; give every XCD a
@@ -501,6 +531,7 @@ __global__ __launch_bounds__(256) void k_elem(
     if (kick) t1 = t1 + p.dt;
     const double hp = (predict && drift) ? 0.5 * (kick ? dtn : p.dt) : 0.0;
     p.tau = (t1 + hp) - tr;
+    gox_set(p);
     if (gid == 0) {
       double *cw = p.clk + CK_SLOT * (kick ? p.par ^ 1 : p.par);
       if (kick) {
@@ -1391,6 +1422,7 @@ __device__ __forceinline__ double elem_clock(KP &p, double rmax, int predict,
   p.h = 0.5 * p.dt;
   const double t1 = ck[CK_T] + p.dt, tr = ck[CK_TR];
   p.tau = (t1 + (predict ? 0.5 * dtn : 0.0)) - tr;
+  gox_set(p);
   if (writer) {
     double *cw = p.clk + CK_SLOT * (p.par ^ 1);
     cw[CK_DT] = dtn;
@@ -1749,9 +1781,11 @@ __global__ __launch_bounds__(512) void k_recon(
     int *__restrict__ aout, double *__restrict__ dpart,
     unsigned long long *__restrict__ ovf) {
   const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
+  int bx, gy;
+  tile_split(p, t, bx, gy);
   clock_tau(p);
   recon_tile<FT, MODE, PER>(p, rec, qm, cnt, lst, flags, F, part, fout, aout,
-                            dpart, ovf, t % p.nbx, t / p.nbx);
+                            dpart, ovf, bx, gy);
 }
 
 // Resampling value at every site (section 2.3.2): nearest element, the
@@ -1855,9 +1889,11 @@ __global__ __launch_bounds__(512) void k_remap_eval(
     const FT *__restrict__ C, FT *__restrict__ Fout,
     unsigned long long *__restrict__ ovf) {
   const int t = xcd_tile(blockIdx.x, p.nbx * p.ngy);
+  int bx, gy;
+  tile_split(p, t, bx, gy);
   clock_tau(p);
-  remap_tile<FT, TO_F, PER>(p, rec, qm, cnt, lst, flags, C, Fout, ovf,
-                            t % p.nbx, t / p.nbx);
+  remap_tile<FT, TO_F, PER>(p, rec, qm, cnt, lst, flags, C, Fout, ovf, bx,
+                            gy);
 }
 
 // Diagnostics (section 3.2): sums of the per-workgroup partials, potential
