@@ -612,30 +612,31 @@ __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
   const double dx = image_dx<PER>(p, xP - r[R_X]), dv = vP - r[R_V];
   const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
   const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
-  if (fabs(lx) < p.dxm && fabs(lv) < p.dvm) {
-    const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
-    const double ux = fma(r[R_HXXX], pxx, fma(r[R_H2XXV], pxv, r[R_HXVV] * pvv));
-    const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
-    const double dqx = fma(r[R_AXX], ux, fma(r[R_AXV], uv, lx));
-    const double dqv = fma(r[R_AVX], ux, fma(r[R_AVV], uv, lv));
-    double d2;
-    if (R2) {
-      d2 = fma(dqx, dqx, dqv * dqv);
-    } else {
-      const double zx = dqx * p.rx, zv = dqv * p.rv;
-      d2 = fma(zx, zx, zv * zv);
-    }
-    // (d2, id) order; an exact tie of d2 is rare, so the id comparison is
-    // made only when some lane of the wavefront has one
-    bool upd = d2 < bd;
-    const bool tie = d2 == bd;
-    if (__builtin_expect(__ballot(tie) != 0ull, 0)) upd = upd || (tie && e < best);
-    if (upd) {
-      bd = d2;
-      best = e;
-      bdqx = dqx;
-      bdqv = dqv;
-    }
+  // evaluated on every lane (a candidate is valid on some lane of the
+  // block almost always), the validity folded into the update
+  const bool valid = fabs(lx) < p.dxm && fabs(lv) < p.dvm;
+  const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
+  const double ux = fma(r[R_HXXX], pxx, fma(r[R_H2XXV], pxv, r[R_HXVV] * pvv));
+  const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
+  const double dqx = fma(r[R_AXX], ux, fma(r[R_AXV], uv, lx));
+  const double dqv = fma(r[R_AVX], ux, fma(r[R_AVV], uv, lv));
+  double d2;
+  if (R2) {
+    d2 = fma(dqx, dqx, dqv * dqv);
+  } else {
+    const double zx = dqx * p.rx, zv = dqv * p.rv;
+    d2 = fma(zx, zx, zv * zv);
+  }
+  // (d2, id) order; an exact tie of d2 is rare, so the id comparison is
+  // made only when some lane of the wavefront has one
+  bool upd = valid && d2 < bd;
+  const bool tie = valid && d2 == bd;
+  if (__builtin_expect(__ballot(tie) != 0ull, 0)) upd = upd || (tie && e < best);
+  if (upd) {
+    bd = d2;
+    best = e;
+    bdqx = dqx;
+    bdqv = dqv;
   }
 }
 
