@@ -604,7 +604,7 @@ __global__ __launch_bounds__(256) void k_fill(T *__restrict__ a, long long n,
 // rounding step).  With R2 (rx == rv == r, a power of two) d^2 is ranked
 // as |dQ|^2 = d^2 / r^2: the same scaling argument makes the two orders
 // (and their ties) identical.
-template <int PER, bool R2, typename R>
+template <int PER, bool R2, bool BF, typename R>
 __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
                                                 double xP, double vP,
                                                 double &bd, int &best,
@@ -612,9 +612,12 @@ __device__ __forceinline__ void query_candidate(const KP &p, const R &r, int e,
   const double dx = image_dx<PER>(p, xP - r[R_X]), dv = vP - r[R_V];
   const double lx = fma(r[R_AXX], dx, r[R_AXV] * dv);
   const double lv = fma(r[R_AVX], dx, r[R_AVV] * dv);
-  // evaluated on every lane (a candidate is valid on some lane of the
-  // block almost always), the validity folded into the update
   const bool valid = fabs(lx) < p.dxm && fabs(lv) < p.dvm;
+  // BF: evaluated on every lane (a candidate is valid on some lane of the
+  // block almost always), the validity folded into the update; else the
+  // quadratic part runs under the validity mask (kernels held to few
+  // registers keep their live ranges short that way)
+  if (!BF && !valid) return;
   const double pxx = lx * lx, pxv = lx * lv, pvv = lv * lv;
   const double ux = fma(r[R_HXXX], pxx, fma(r[R_H2XXV], pxv, r[R_HXVV] * pvv));
   const double uv = fma(r[R_HVXX], pxx, fma(r[R_H2VXV], pxv, r[R_HVVV] * pvv));
@@ -734,7 +737,7 @@ __device__ __forceinline__ void stage_wait() {
 
 // The candidates of one staged round, unrolled: the record offsets are
 // immediate and the ids scalar loads of the (uniform) list row.
-template <int PER, bool R2>
+template <int PER, bool R2, bool BF>
 __device__ __forceinline__ void query_round(
     const KP &p, const int *__restrict__ L, int c0, int m, const double *stage,
     double xP, double vP, double &bd, int &best, double &dqx, double &dqv) {
@@ -745,7 +748,7 @@ __device__ __forceinline__ void query_round(
       Rec r;
 #pragma unroll
       for (int q = 0; q < RS; ++q) r.v[q] = stage[k * RS + q];
-      query_candidate<PER, R2>(p, r, e, xP, vP, bd, best, dqx, dqv);
+      query_candidate<PER, R2, BF>(p, r, e, xP, vP, bd, best, dqx, dqv);
     }
   }
 }
@@ -758,7 +761,7 @@ __device__ __forceinline__ void query_round(
 // L is the block's list row, id0 its first entries (lane-indexed, loaded by
 // the caller together with the count n).  With staged0, the caller has
 // already issued and waited for the first round (stage_issue, stage_wait).
-template <int PER, bool R2>
+template <int PER, bool R2, bool BF>
 __device__ __forceinline__ int query_block_r(
     const KP &p, const double *__restrict__ rec, const int *__restrict__ L,
     int id0, int n, bool scan_all, double xP, double vP, double &dqx,
@@ -774,28 +777,28 @@ __device__ __forceinline__ int query_block_r(
         stage_issue(rec, L, id0, c0, m, stage);
         stage_wait();
       }
-      query_round<PER, R2>(p, L, c0, m, stage, xP, vP, bd, best, dqx, dqv);
+      query_round<PER, R2, BF>(p, L, c0, m, stage, xP, vP, bd, best, dqx, dqv);
       wave_sync();
     }
   } else {
     for (int e = 0; e < p.E; ++e) {
       Rec r;
       load_rec(rec, e, r);
-      query_candidate<PER, R2>(p, r, e, xP, vP, bd, best, dqx, dqv);
+      query_candidate<PER, R2, BF>(p, r, e, xP, vP, bd, best, dqx, dqv);
     }
   }
   return best;
 }
 
-template <int PER>
+template <int PER, bool BF = false>
 __device__ __forceinline__ int query_block(
     const KP &p, const double *__restrict__ rec, const int *__restrict__ L,
     int id0, int n, bool scan_all, double xP, double vP, double &dqx,
     double &dqv, double *stage, bool staged0 = false) {
-  return p.r2 ? query_block_r<PER, true>(p, rec, L, id0, n, scan_all, xP, vP,
-                                          dqx, dqv, stage, staged0)
-              : query_block_r<PER, false>(p, rec, L, id0, n, scan_all, xP, vP,
-                                           dqx, dqv, stage, staged0);
+  return p.r2 ? query_block_r<PER, true, BF>(p, rec, L, id0, n, scan_all, xP,
+                                              vP, dqx, dqv, stage, staged0)
+              : query_block_r<PER, false, BF>(p, rec, L, id0, n, scan_all, xP,
+                                               vP, dqx, dqv, stage, staged0);
 }
 
 // ------------------------------------------------------- interpolations
@@ -1634,7 +1637,7 @@ __device__ __forceinline__ int lattice_col(const KP &p, int k, double &shift) {
 // partials of its row group (the strips in order); the field adds the
 // groups in increasing order.  No workgroup waits on another, so the
 // launch needs no device-scope synchronisation.
-template <typename FT, int MODE, int PER>
+template <typename FT, int MODE, int PER, bool BF = false>
 __device__ __forceinline__ void recon_tile(
     KP p, const double *__restrict__ rec, const double *__restrict__ qm,
     const int *__restrict__ cnt,
@@ -1664,8 +1667,8 @@ __device__ __forceinline__ void recon_tile(
     if (scan_all && lane == 0 && n > p.cap) atomicAdd(ovf, 1ull);
     const double xP = site_x(p, i), vP = site_v(p, j);
     double dqx, dqv;
-    best = query_block<PER>(p, rec, L, id0, n, scan_all, xP, vP, dqx, dqv,
-                            qstage[w]);
+    best = query_block<PER, BF>(p, rec, L, id0, n, scan_all, xP, vP, dqx,
+                                dqv, qstage[w]);
     if (live && best >= 0) {
       const double Qx = qm[2 * (size_t)best] + dqx;
       const double Qv = qm[2 * (size_t)best + 1] + dqv;
@@ -1785,8 +1788,10 @@ __global__ __launch_bounds__(512) void k_recon(
   int bx, gy;
   tile_split(p, t, bx, gy);
   clock_tau(p);
-  recon_tile<FT, MODE, PER>(p, rec, qm, cnt, lst, flags, F, part, fout, aout,
-                            dpart, ovf, bx, gy);
+  // branch-free candidates (as many registers as it takes; the batched
+  // kernel, held to 64, keeps the masked form)
+  recon_tile<FT, MODE, PER, true>(p, rec, qm, cnt, lst, flags, F, part, fout,
+                                  aout, dpart, ovf, bx, gy);
 }
 
 // Resampling value at every site (section 2.3.2): nearest element, the
