@@ -277,7 +277,17 @@ int launch_elem(vp_ctx *c, int kick, int drift, int predict, int reg,
   const long long nbz = zero_buf >= 0 ? c->L.nb : 0;
   const long long n =
       std::max<long long>(k.E, std::min<long long>(nbz, 1 << 22));
-  hipLaunchKernelGGL(k_elem, dim3(grid_for(n, 256)), dim3(256), 0, c->stream,
+  // the workgroup table pays where the device atomics queue: many patches
+  // of boxes of at most TABLE_RB blocks (strides up to 8).  A launch of a
+  // few waves per SIMD waits on their latency instead, and with stride 16
+  // (boxes of ~30 blocks) the table was slower too.
+  const int np = elem_patches(k.mx, k.mv);
+  const bool tab = np >= ELEM_TABLE_MIN_PATCHES && k.sx <= 8 && k.sv <= 8;
+  const unsigned grid =
+      tab ? std::max<unsigned>(grid_for(n, 256), (unsigned)np)
+          : grid_for(n, 256);
+  auto kern = tab ? k_elem<true> : k_elem<false>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c->stream,
                      k, c->at<double>(c->L.st), c->at<double>(c->L.acc),
                      c->at<double>(c->L.rec), c->at<double>(c->L.qm),
                      zero_buf >= 0 ? c->counts(zero_buf) : nullptr, nbz,

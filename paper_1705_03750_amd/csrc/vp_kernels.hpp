@@ -443,14 +443,15 @@ __device__ __forceinline__ RegBox elem_record_box(
 }
 
 // Block (row qr, column qc) of a registration box: its list index, or -1
-// when the element's validity window cannot reach it.
+// when the element's validity window cannot reach it; bvq and bxq receive
+// its block row and (unwrapped) block column.
 template <bool TALL>
 __device__ __forceinline__ int reg_block(const KP &p, const RegBox &B, int qr,
-                                         int qc) {
-  const int bvq = B.b0v + qr;
+                                         int qc, int &bvq, int &bxq) {
+  bvq = B.b0v + qr;
   const int gy = group_of_brow(p, bvq);
   const int o = TALL ? group_ox(p, gy) : (B.opack >> (3 * (gy - B.ga))) & 7;
-  const int bxq = blk(B.ilo, o, 1) + qc;
+  bxq = blk(B.ilo, o, 1) + qc;
   const int i0 = o + 8 * (bxq - 1), j0 = p.ov + 8 * (bvq - p.obv);
   const double cx = (p.x_min + (double)(i0 + 4) * p.dx) - B.x;
   const double cv = (p.v_min + (double)(j0 + 4) * p.dv) - B.v;
@@ -475,7 +476,8 @@ __device__ __forceinline__ void reg_claims(const KP &p, const RegBox &B,
     for (int k = 0; k < RB; ++k) {
       bb[k] = -1;
       if (qb + k < B.n) {
-        bb[k] = reg_block<TALL>(p, B, qr, qc);
+        int bvq, bxq;
+        bb[k] = reg_block<TALL>(p, B, qr, qc, bvq, bxq);
         if (++qc == B.wxm) {
           qc = 0;
           ++qr;
@@ -500,6 +502,95 @@ __device__ __forceinline__ void reg_direct(const KP &p, const RegBox &B,
     reg_claims<false>(p, B, q0, e, cnt, lst);
 }
 
+// The element passes take elements in PATCH x PATCH lattice patches, one per
+// 256-thread workgroup: the block lists an element registers into are mostly
+// those of its neighbours in the same workgroup.
+constexpr int PATCH = 16;
+
+// Number of element patches of a run.
+__host__ __device__ __forceinline__ int elem_patches(int mx, int mv) {
+  return ((mx + PATCH - 1) / PATCH) * ((mv + PATCH - 1) / PATCH);
+}
+
+// Registration of a workgroup's elements through a table of block counters
+// in LDS (RT block rows by RT block columns around the workgroup's element
+// patch, rows from tr0 and columns from tc0).  Every claim of a block inside
+// the table takes a rank among the workgroup's claims on it (LDS atomic);
+// the first claimer of each block then takes the workgroup's slots of it
+// with one device atomic (the base), and each claim writes its id at
+// base + rank.  A claim outside the table, and the blocks of a box past the
+// RB-th, take their slots one by one as in reg_claims.  The counts, and
+// with them the readers' overflow test, are those of one atomic per claim;
+// only the order of the ids within a list changes, which the query does not
+// depend on (it ranks by distance, then id).  Every thread of the workgroup
+// must call it: it holds two workgroup barriers.
+constexpr int RT = 64;
+// element passes with fewer patches than this register directly
+constexpr int ELEM_TABLE_MIN_PATCHES = 1024;
+
+template <int RB, bool TALL>
+__device__ __forceinline__ void reg_table_rank(const KP &p, const RegBox &B,
+                                               int tr0, int tc0,
+                                               int *__restrict__ rtab,
+                                               int (&bb)[RB], int (&key)[RB],
+                                               int (&loc)[RB]) {
+  int qr = 0, qc = 0;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    bb[k] = -1;
+    key[k] = -1;
+    loc[k] = 0;
+    if (k < B.n) {
+      int bvq, bxq;
+      bb[k] = reg_block<TALL>(p, B, qr, qc, bvq, bxq);
+      if (++qc == B.wxm) {
+        qc = 0;
+        ++qr;
+      }
+      const unsigned r = (unsigned)(bvq - tr0), c = (unsigned)(bxq - tc0);
+      if (bb[k] >= 0 && r < (unsigned)RT && c < (unsigned)RT) {
+        key[k] = (int)(r * RT + c);
+        loc[k] = atomicAdd(&rtab[key[k]], 1);
+      }
+    }
+  }
+}
+
+template <int RB>
+__device__ __forceinline__ void reg_table(const KP &p, const RegBox &B,
+                                          int e, int tr0, int tc0,
+                                          int *__restrict__ rtab,
+                                          int *__restrict__ cnt,
+                                          int *__restrict__ lst) {
+  int bb[RB], key[RB], loc[RB], slot[RB];
+  if (B.n > 0 && B.n / B.wxm > REG_NEAR_ROWS)
+    reg_table_rank<RB, true>(p, B, tr0, tc0, rtab, bb, key, loc);
+  else
+    reg_table_rank<RB, false>(p, B, tr0, tc0, rtab, bb, key, loc);
+  __syncthreads();
+  // device atomics: one per block of the table (its first claimer), one
+  // per claim outside it, all issued before any result is used
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    slot[k] = p.cap;
+    if (bb[k] >= 0 && key[k] < 0)
+      slot[k] = atomicAdd(&cnt[bb[k]], 1);
+    else if (key[k] >= 0 && loc[k] == 0)
+      slot[k] = atomicAdd(&cnt[bb[k]], rtab[key[k]]);
+  }
+#pragma unroll
+  for (int k = 0; k < RB; ++k)
+    if (key[k] >= 0 && loc[k] == 0) rtab[key[k]] = slot[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    if (bb[k] < 0) continue;
+    const int sl = key[k] >= 0 ? rtab[key[k]] + loc[k] : slot[k];
+    if (sl < p.cap) lst[(size_t)bb[k] * p.cap + sl] = e;
+  }
+  if (B.n > RB) reg_direct(p, B, RB, e, cnt, lst);
+}
+
 __device__ __forceinline__ void elem_record(
     const KP &p, const ElemState &s, int e, double *__restrict__ rec,
     double *__restrict__ qm, int *__restrict__ cnt, int *__restrict__ lst,
@@ -508,16 +599,34 @@ __device__ __forceinline__ void elem_record(
   if (B.n > 0) reg_direct(p, B, 0, e, cnt, lst);
 }
 
+// TAB false: thread gid takes element gid and registers every claim with
+// its own device atomic (reg_direct).  TAB true: workgroup w takes lattice
+// patch w and registers the first TABLE_RB blocks of each box through the
+// workgroup's table (reg_table); the grid then covers every patch.
+constexpr int TABLE_RB = 16;
+template <bool TAB>
 __global__ __launch_bounds__(256) void k_elem(
     KP p, double *__restrict__ st, const double *__restrict__ acc,
     double *__restrict__ rec, double *__restrict__ qm,
     int *__restrict__ cnt_zero, long long nb_zero,
     int *__restrict__ cnt_reg, int *__restrict__ lst, int *__restrict__ flags,
     int kick, int drift, int predict, int reg) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ int rtab[TAB ? RT * RT : 1];
+  const int tid = threadIdx.x;
+  const long long gid = (long long)blockIdx.x * blockDim.x + tid;
   const long long gsz = (long long)gridDim.x * blockDim.x;
+  if (TAB && predict)
+    for (int i = tid; i < RT * RT; i += 256) rtab[i] = 0;
   for (long long b = gid; b < nb_zero; b += gsz) cnt_zero[b] = 0;
-  const int e = (int)gid;
+  // this thread's element: gid, or (k, l) in lattice patch blockIdx.x
+  const int npx = (p.mx + PATCH - 1) / PATCH;
+  const int pat = blockIdx.x;
+  const int ek = (pat % npx) * PATCH + tid % PATCH;
+  const int el = (pat / npx) * PATCH + tid / PATCH;
+  const bool has =
+      TAB ? pat < elem_patches(p.mx, p.mv) && ek < p.mx && el < p.mv
+          : gid < p.E;
+  const int e = !has ? 0 : TAB ? el * p.mx + ek : (int)gid;
   // variable step: this step's dt from the clock; after a kick, the next
   // step's from the density the field kernel saw
   double t1 = 0.0, tr = 0.0, dtn = p.dt;
@@ -542,15 +651,29 @@ __global__ __launch_bounds__(256) void k_elem(
       cw[CK_TAU] = p.tau;
     }
   }
-  if (e >= p.E) return;
   const size_t E = (size_t)p.E;
   ElemState s;
-  elem_load(st, E, e, s);
-  if (kick) elem_kick(p, AccTable{acc, p.nx + 8}, s);
-  if (p.clk && kick) p.h = 0.5 * dtn;
-  if (predict && drift) elem_drift(p, s);
-  if (kick || (predict && drift)) elem_store(st, E, e, s);
-  if (predict) elem_record(p, s, e, rec, qm, cnt_reg, lst, flags, reg);
+  RegBox B;
+  B.n = 0;
+  if (has) {
+    elem_load(st, E, e, s);
+    if (kick) elem_kick(p, AccTable{acc, p.nx + 8}, s);
+    if (p.clk && kick) p.h = 0.5 * dtn;
+    if (predict && drift) elem_drift(p, s);
+    if (kick || (predict && drift)) elem_store(st, E, e, s);
+    if (predict) B = elem_record_box(p, s, e, rec, qm, flags, reg);
+  }
+  if (!predict) return;
+  if (TAB) {
+    // the registration table is centred on the patch's lattice sites
+    const int tr0 =
+        blk(p.sv * ((pat / npx) * PATCH + PATCH / 2), p.ov, p.obv) - RT / 2;
+    const int tc0 =
+        blk(p.sx * ((pat % npx) * PATCH + PATCH / 2), 0, 1) - RT / 2;
+    reg_table<TABLE_RB>(p, B, e, tr0, tc0, rtab, cnt_reg, lst);
+  } else if (B.n > 0) {
+    reg_direct(p, B, 0, e, cnt_reg, lst);
+  }
 }
 
 // New isotropic elements (P = Q_m, T = I, H = 0) and cleared block counts.
@@ -1498,17 +1621,7 @@ __global__ __launch_bounds__(64) void k_field_chunks(
 // and registers its elements.  Every load the field needs is issued in one
 // round trip together with the element state.
 constexpr int ELEMC_WG = 256;
-// Elements come in PATCH x PATCH lattice patches, one per workgroup: the
-// block lists an element registers into are mostly those of its neighbours
-// in the same workgroup, which keeps the slot claims of a workgroup on few
-// cache lines of the counts.
-constexpr int PATCH = 16;
 static_assert(PATCH * PATCH == ELEMC_WG, "one element per thread");
-
-// Number of element patches of a run.
-__host__ __device__ __forceinline__ int elem_patches(int mx, int mv) {
-  return ((mx + PATCH - 1) / PATCH) * ((mv + PATCH - 1) / PATCH);
-}
 
 __global__ __launch_bounds__(ELEMC_WG) void k_elem_window(
     KP p, const double *__restrict__ Mc, const double *__restrict__ ctot,

@@ -126,6 +126,32 @@ def test_density_and_poisson_wide_grids(vp, orc, nx):
     g.sync()
 
 
+def test_registration_through_workgroup_tables(vp, orc):
+    """Element passes over many patches of 16 x 16 elements with strides up
+    to 8 register their slot claims through a table per workgroup (one
+    device atomic per block and workgroup).  4104 x 4096 sites, s = 8:
+    33 x 32 patches, the last column of patches 1 element wide.  T is
+    perturbed by up to 0.3, so windows reach ~13 sites and boxes up to
+    5 x 5 blocks, past the 16 the table takes (the rest claim directly).
+    The assignment of the injected state, then the elements and f after
+    two steps (the separate field kernel: more than 2048 columns), against
+    the oracle."""
+    nx, nv = 4104, 4096
+    p = params(nx, 8, nv=nv)
+    print(f"[table registration] {nx}x{nv} s=8", flush=True)
+    o, g = pair(vp, orc, p, halos(nx, nv, seed=nx))
+    el = perturbed(o, 21, amp_x=0.3, amp_t=0.3, amp_h=0.5)
+    o.set_elements(el)
+    g.set_elements(el)
+    a_gpu = g.assignment().cpu().numpy()
+    assert np.array_equal(a_gpu, o.assignment())
+    o.step(2)
+    g.step(2)
+    assert_elements_close(g.get_elements().cpu().numpy(), o)
+    assert rel_linf(g.reconstruct_f().cpu().numpy(), o.reconstruct_f()) <= RTOL
+    g.sync()
+
+
 @pytest.mark.parametrize("mode", ["free", "constant", "harmonic",
                                   "anharmonic"])
 def test_element_motion_matches_oracle(vp, orc, mode):
