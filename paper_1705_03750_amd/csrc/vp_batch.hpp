@@ -47,7 +47,8 @@ enum {
 // Element-pass argument bits.
 enum {
   EA_KICK = 1, EA_DRIFT = 2, EA_PRED = 4, EA_REG = 8, EA_REGBUF1 = 16,
-  EA_ZERO = 32, EA_ZEROBUF1 = 64, EA_RESET = 128
+  EA_ZERO = 32, EA_ZEROBUF1 = 64, EA_RESET = 128,
+  EA_TAB = 256  // item = lattice patch, slot claims through reg_table
 };
 
 template <typename FT>
@@ -74,11 +75,16 @@ __device__ __forceinline__ int find_run(const PhaseTable *__restrict__ t,
 }
 
 // Element passes (predict / kick / remap records / reset / count clearing):
-// 256 elements and 256 block counts per item.
+// 256 elements and 256 block counts per item; with EA_TAB the item's
+// elements are lattice patch item - begin and their slot claims go through
+// the workgroup's table (the flag is uniform over an item, so every thread
+// of the workgroup reaches the table's barriers).
 template <typename FT>
 __global__ __launch_bounds__(256) void kb_elem(
     const RunDesc<FT> *__restrict__ runs, const PhaseTable *__restrict__ tab) {
+  __shared__ int rtab[RT * RT];
   const int total = tab->total;
+  const int tid = threadIdx.x;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int q = find_run(tab, item);
     const PhaseItem pi = tab->it[q];
@@ -87,14 +93,50 @@ __global__ __launch_bounds__(256) void kb_elem(
     p.tau = 0.5 * p.dt * pi.h;
     gox_set(p);
     const int arg = pi.arg;
-    const long long idx = (long long)(item - pi.begin) * 256 + threadIdx.x;
+    const bool tabm = arg & EA_TAB;
+    if (tabm) {
+      // the previous item's table reads are done before it is cleared
+      __syncthreads();
+      for (int i = tid; i < RT * RT; i += 256) rtab[i] = 0;
+    }
+    const int local = item - pi.begin;
+    const long long idx = (long long)local * 256 + tid;
     if (arg & EA_ZERO) {
       int *cz = R.cnt + ((arg & EA_ZEROBUF1) ? R.nb : 0);
       if (idx < R.nb) cz[idx] = 0;
     }
-    if (idx >= p.E) continue;
-    const int e = (int)idx;
+    const int npx = (p.mx + PATCH - 1) / PATCH;
+    const int ek = (local % npx) * PATCH + tid % PATCH;
+    const int el = (local / npx) * PATCH + tid / PATCH;
+    const bool has = tabm ? local < elem_patches(p.mx, p.mv) && ek < p.mx &&
+                                el < p.mv
+                          : idx < p.E;
+    const int e = !has ? 0 : tabm ? el * p.mx + ek : (int)idx;
     const size_t E = (size_t)p.E;
+    if (tabm) {
+      const bool kick = arg & EA_KICK, drift = arg & EA_DRIFT;
+      ElemState s;
+      RegBox B;
+      B.n = 0;
+      if (has) {
+        elem_load(R.st, E, e, s);
+        if (kick) elem_kick(p, AccTable{R.acc, p.nx + 8}, s);
+        if (drift) elem_drift(p, s);
+        if (kick || drift) elem_store(R.st, E, e, s);
+        B = elem_record_box(p, s, e, R.rec, R.qm, R.flags,
+                            (arg & EA_REG) ? 1 : 0);
+      }
+      const int tr0 =
+          blk(p.sv * ((local / npx) * PATCH + PATCH / 2), p.ov, p.obv) -
+          RT / 2;
+      const int tc0 =
+          blk(p.sx * ((local % npx) * PATCH + PATCH / 2), 0, 1) - RT / 2;
+      __syncthreads();  // the cleared table
+      reg_table<TABLE_RB>(p, B, e, tr0, tc0, rtab,
+                          R.cnt + ((arg & EA_REGBUF1) ? R.nb : 0), R.lst);
+      continue;
+    }
+    if (!has) continue;
     if (arg & EA_RESET) {
       const int k = e % p.mx, l = e / p.mx;
       for (int s = 0; s < NSTATE; ++s) R.st[s * E + e] = 0.0;

@@ -1397,14 +1397,24 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
     vp_ctx *c = sl.c;
     const KP &k = c->k;
     const int cur = c->cur;
-    const int el_items = ceil_div(k.E, 256);
-    const int elz_items = ceil_div(std::max<long long>(k.E, c->L.nb), 256);
+    // predict items of strides up to 8 take one lattice patch each and
+    // claim their list slots through the workgroup's table (EA_TAB): a
+    // tick's element launch spans every resident run, where the device
+    // atomics queue
+    const bool tabr = k.sx <= 8 && k.sv <= 8;
+    const int tb = tabr ? EA_TAB : 0;
+    const long long pe =
+        tabr ? std::max<long long>(k.E, 256LL * elem_patches(k.mx, k.mv))
+             : k.E;
+    const int el_items = ceil_div(pe, 256);
+    const int elz_items = ceil_div(std::max<long long>(pe, c->L.nb), 256);
     const int tiles = k.nbx * k.ngy;
     const int regb = cur ? EA_REGBUF1 : 0, zb = cur ? EA_ZEROBUF1 : 0;
     const int since = (int)(sl.done - c->reset_step);
     if (sl.need_predict) {
       sl.list_h = 2 * since + 1;
-      add(PH_PRED, q, el_items, EA_PRED | EA_DRIFT | EA_REG | regb, sl.list_h);
+      add(PH_PRED, q, el_items, EA_PRED | EA_DRIFT | EA_REG | regb | tb,
+          sl.list_h);
     }
     add(PH_RECON, q, tiles, cur, sl.list_h);
     add(PH_FIELD, q, (k.nx + FIELD_WG - 1) / FIELD_WG, 0);
@@ -1415,7 +1425,7 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
       sl.list_h = 2 * (step_after - (int)c->reset_step) + 1;
       add(PH_KICK, q, elz_items,
           EA_KICK | EA_DRIFT | EA_PRED | EA_REG | (cur ? 0 : EA_REGBUF1) |
-              EA_ZERO | zb, sl.list_h);
+              EA_ZERO | zb | tb, sl.list_h);
       c->cur ^= 1;
       sl.need_predict = false;
     } else {
@@ -1426,7 +1436,7 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
     const int regr = cr ? EA_REGBUF1 : 0, zr = cr ? EA_ZEROBUF1 : 0;
     if (remap_due) {
       const int hr = 2 * (step_after - (int)c->reset_step);
-      add(PH_RM_PRED, q, el_items, EA_PRED | EA_REG | regr, hr);
+      add(PH_RM_PRED, q, el_items, EA_PRED | EA_REG | regr | tb, hr);
       add(PH_RM_EVAL, q, tiles, cr, hr);
       const int sx = c->mixed() ? fit_segments<float>(k.nx)
                                 : fit_segments<double>(k.nx);
@@ -1440,7 +1450,7 @@ void build_tick(vp_server *s, PhaseTable *tab, std::vector<int> &finishing) {
     }
     if (finish) {
       const int hf = 2 * (step_after - (int)c->reset_step);
-      add(PH_FIN_PRED, q, el_items, EA_PRED | EA_REG | regr, hf);
+      add(PH_FIN_PRED, q, el_items, EA_PRED | EA_REG | regr | tb, hf);
       add(PH_FIN_RECON, q, tiles, cr, hf);
       add(PH_FIN_ZERO, q, ceil_div(c->L.nb, 256), EA_ZERO | zr);
       finishing.push_back(q);
