@@ -68,6 +68,9 @@ def pair(vp, orc, p, f0, precision="fp64"):
     (128, 64, 8, 0.25, 21, 8, "gravity, shared field"),
     (2048, 32, 8, -0.5, 10, 4, "plasma, field per workgroup"),
     (2304, 32, 8, -0.5, 10, 4, "plasma, separate field kernel"),
+    # 64 x 16 patches of 16 x 16 elements: slot claims through the
+    # workgroup tables, whose keys take unwrapped block columns at the seam
+    (4096, 1024, 4, -0.5, 6, 4, "plasma, separate field kernel, tables"),
 ])
 def test_fp64_periodic_matches_oracle(vp, orc, nx, nv, s, G, steps, n_s,
                                       path):
