@@ -525,7 +525,10 @@ __host__ __device__ __forceinline__ int elem_patches(int mx, int mv) {
 // depend on (it ranks by distance, then id).  Every thread of the workgroup
 // must call it: it holds two workgroup barriers.
 constexpr int RT = 64;
-// element passes with fewer patches than this register directly
+// Element passes with fewer patches than this register directly: with a
+// workgroup or so per CU the claims wait on the atomics' latency, which the
+// table's barriers lengthen (measured: 256 patches slower with the table,
+// 1024 and 4096 faster).
 constexpr int ELEM_TABLE_MIN_PATCHES = 1024;
 
 template <int RB, bool TALL>
