@@ -126,19 +126,21 @@ def test_density_and_poisson_wide_grids(vp, orc, nx):
     g.sync()
 
 
-def test_registration_through_workgroup_tables(vp, orc):
+@pytest.mark.parametrize("nx,nv,sx,sv", [(4104, 4096, 8, 8),
+                                         (4096, 2056, 4, 8)])
+def test_registration_through_workgroup_tables(vp, orc, nx, nv, sx, sv):
     """Element passes over many patches of 16 x 16 elements with strides up
     to 8 register their slot claims through a table per workgroup (one
     device atomic per block and workgroup).  4104 x 4096 sites, s = 8:
-    33 x 32 patches, the last column of patches 1 element wide.  T is
+    33 x 32 patches, the last column of patches 1 element wide; T is
     perturbed by up to 0.3, so windows reach ~13 sites and boxes up to
     5 x 5 blocks, past the 16 the table takes (the rest claim directly).
-    The assignment of the injected state, then the elements and f after
-    two steps (the separate field kernel: more than 2048 columns), against
-    the oracle."""
-    nx, nv = 4104, 4096
-    p = params(nx, 8, nv=nv)
-    print(f"[table registration] {nx}x{nv} s=8", flush=True)
+    4096 x 2056 sites with strides 4 along x and 8 along v: 64 x 17
+    patches, the last row of patches 1 element high.  The assignment of
+    the injected state, then the elements and f after two steps (the
+    separate field kernel: more than 2048 columns), against the oracle."""
+    p = params(nx, sx, nv=nv, sv=sv)
+    print(f"[table registration] {nx}x{nv} sx={sx} sv={sv}", flush=True)
     o, g = pair(vp, orc, p, halos(nx, nv, seed=nx))
     el = perturbed(o, 21, amp_x=0.3, amp_t=0.3, amp_h=0.5)
     o.set_elements(el)
