@@ -60,6 +60,8 @@ def pair(vp, orc, p, f0, precision="fp64"):
     (128, 128, 8, 24, 10, "shared field"),
     (2048, 32, 8, 12, 5, "field per workgroup"),
     (2304, 32, 8, 12, 5, "separate field kernel"),
+    # 64 x 16 patches: the element pass claims slots through workgroup tables
+    (4096, 1024, 4, 6, 3, "separate field kernel, tables"),
 ])
 def test_fp64_variable_step_matches_oracle(vp, orc, nx, nv, s, steps, n_s,
                                            path):
